@@ -1,0 +1,66 @@
+// common.hpp -- shared launch-side definitions of the HIP library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nphc.h"
+
+namespace nphc {
+
+constexpr int kMaxM = NPHC_MAX_N - 1;      // free spins
+constexpr int kMaxClasses = NPHC_MAX_N;    // one queue class per ring size
+constexpr int kBatchMaxM = 8;              // rings of mixed size: N <= 9
+
+// One class = all systems of one ring size, a contiguous range of items.
+struct ClassDesc {
+    int32_t M;
+    int32_t pad;
+    int64_t item_lo, item_hi;
+};
+
+// Work-queue state, in the caller's workspace.
+struct QueueState {
+    unsigned long long next[kMaxClasses];  // next queue position per class
+    int64_t qhi[kMaxClasses];              // end of the class's positions
+};
+
+struct TrackOptsDev {
+    double h0, hmax, hmin, corr_tol, R_inf, t_stall, t_end;
+    int32_t max_corr, max_steps, predictor, pad;
+};
+
+struct TrackArgs {
+    // batch
+    int32_t num_systems;
+    int32_t num_classes;
+    const int32_t* N;          // device
+    const int64_t* path_off;   // device, num_systems + 1
+    const double* gamma;       // device, 2 per system
+    const void* Jpack;         // device, packed couplings in the tracking type
+    const int64_t* Jpack_off;  // device, per system
+    ClassDesc cls[kMaxClasses];
+    // work list
+    const int64_t* ids;        // device or null (= all items)
+    QueueState* q;             // device workspace
+    TrackOptsDev o;
+    // outputs, indexed by queue position
+    int64_t out_stride;        // >= number of positions
+    double* z;                 // 2 * n_max planes of out_stride doubles (re, im per unknown)
+    double* t;
+    int32_t* status;
+    int32_t* accepted;
+    int32_t* rejected;
+};
+
+__device__ __forceinline__ int64_t find_system(const int64_t* path_off, int32_t num_systems,
+                                               int64_t item)
+{
+    int32_t lo = 0, hi = num_systems;  // path_off[lo] <= item < path_off[hi]
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (path_off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace nphc

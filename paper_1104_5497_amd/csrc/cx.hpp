@@ -1,0 +1,62 @@
+// cx.hpp -- minimal complex arithmetic on a real type T (float or double),
+// usable in device code and, for host-side checks, in host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace nphc {
+
+template <class T>
+struct cx {
+    T re, im;
+};
+
+template <class T> __host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> __host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, T s) { return {s * a.re, s * a.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <class T> __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <class T> __host__ __device__ __forceinline__ T abs1(cx<T> a) { return fabs(a.re) + fabs(a.im); }
+template <class T> __host__ __device__ __forceinline__ T absmax(cx<T> a) { return fmax(fabs(a.re), fabs(a.im)); }
+template <class T> __host__ __device__ __forceinline__ cx<T> sel(bool c, cx<T> a, cx<T> b) { return c ? a : b; }
+
+// c - a * b
+template <class T> __host__ __device__ __forceinline__ cx<T> fnma(cx<T> a, cx<T> b, cx<T> c)
+{
+    return {c.re - a.re * b.re + a.im * b.im, c.im - a.re * b.im - a.im * b.re};
+}
+// c + a * b
+template <class T> __host__ __device__ __forceinline__ cx<T> fma(cx<T> a, cx<T> b, cx<T> c)
+{
+    return {c.re + a.re * b.re - a.im * b.im, c.im + a.re * b.im + a.im * b.re};
+}
+
+// 1 / a, scaled by the larger component so that |a|^2 neither overflows nor
+// underflows for any finite nonzero a.
+template <class T> __host__ __device__ __forceinline__ cx<T> rcp(cx<T> a)
+{
+    T s = absmax(a);
+    T inv_s = T(1) / s;
+    T ar = a.re * inv_s, ai = a.im * inv_s;
+    T d = T(1) / ((ar * ar + ai * ai) * s);
+    return {ar * d, -ai * d};
+}
+
+// principal square root
+template <class T> __host__ __device__ __forceinline__ cx<T> csqrt(cx<T> a)
+{
+    T r = sqrt(sqrt(a.re * a.re + a.im * a.im) * T(0.5) + fabs(a.re) * T(0.5));
+    if (r == T(0)) return {T(0), T(0)};
+    T q = a.im / (T(2) * r);
+    if (a.re >= T(0)) return {r, q};
+    return {fabs(q), a.im >= T(0) ? r : -r};
+}
+
+}  // namespace nphc

@@ -1,0 +1,230 @@
+// xy_lane.hpp -- per-lane homotopy evaluation and Newton/tangent solves for
+// the gauge-fixed XY-ring stationary system, one path per lane.
+//
+// System (paper, eq. (1), with the couplings written as a symmetric matrix J
+// and theta_N = 0, i.e. x_N = 1, y_N = 0):
+//   F_k     = y_k Sx_k - x_k Sy_k,     Sx_k = sum_{j != k} J_kj x_j  (x_N = 1)
+//                                      Sy_k = sum_{j != k} J_kj y_j  (y_N = 0)
+//   F_{M+k} = x_k^2 + y_k^2 - 1,       k = 0..M-1, M = N - 1 free spins.
+// Homotopy (paper, section "NPHC method"): H = gamma (1-t) Q + t F with the
+// start system Q_k = z_k^2 - 1, unknowns z = (x_0..x_{M-1}, y_0..y_{M-1}).
+//
+// Linear solves H_z d = rhs use the structure of the constraint rows, which
+// have exactly two nonzeros: row M+k is a_k dx_k + b_k dy_k = s_k with
+// a_k = 2 t x_k and b_k = 2 (g + t) y_k, g = (1-t) gamma.  Its solutions are
+//   (dx_k, dy_k) = v_k (b_k, -a_k) + (px_k, py_k),
+//   (px_k, py_k) = s_k (conj a_k, conj b_k) / (|a_k|^2 + |b_k|^2),
+// a null-space parametrisation that needs no case split and is well
+// conditioned whenever (a_k, b_k) != 0 (true along every path: a_k = b_k = 0
+// would force (1-t) gamma + t = 0).  Substituting into the gradient rows
+// leaves an M x M complex system in v,
+//   R_kj = A_kj b_j - B_kj a_j,   R v = r - A px - B py,
+// with A = dH_grad/dx and B = dH_grad/dy.  Off the diagonal
+//   R_kj = 2 t J_kj ((g + t) y_j y_k + t x_j x_k),
+// (complex symmetric), on the diagonal
+//   R_kk = (2 g x_k - t Sy_k) b_k - t Sx_k a_k.
+// R is solved by Gaussian elimination with partial pivoting (largest
+// |re|+|im|), the right-hand side carried along, rows exchanged with selects so
+// that the matrix stays in registers.
+#pragma once
+#include "cx.hpp"
+
+namespace nphc {
+
+// Couplings of one system, packed per ring: J[k*M + j] for free spins k, j
+// (zero diagonal) followed by w[k] = J_{k,N} (coupling to the fixed spin).
+template <class T, int M>
+struct Couplings {
+    const T* p;
+    __device__ __forceinline__ T J(int k, int j) const { return p[k * M + j]; }
+    __device__ __forceinline__ T w(int k) const { return p[M * M + k]; }
+};
+
+template <class T, int M>
+struct Point {
+    cx<T> x[M], y[M];
+};
+
+// Sx, Sy and F at z.
+template <class T, int M>
+__device__ __forceinline__ void eval_sums(const Couplings<T, M>& C, const Point<T, M>& z,
+                                          cx<T> Sx[M], cx<T> Sy[M])
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        cx<T> sx = {C.w(k), T(0)};
+        cx<T> sy = {T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j == k) continue;
+            T Jkj = C.J(k, j);
+            sx = sx + Jkj * z.x[j];
+            sy = sy + Jkj * z.y[j];
+        }
+        Sx[k] = sx;
+        Sy[k] = sy;
+    }
+}
+
+
+// Solves H_z(z, t) d = -H(z, t) (newton = true) or -H_t(z, t) (the Davidenko
+// tangent, newton = false).  gamma is the homotopy constant, t in [0, 1] and
+// omt = 1 - t (passed separately so that it keeps its relative precision near
+// t = 1).  Returns false when a pivot vanishes or the result is not finite.
+template <class T, int M>
+__device__ __forceinline__ bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt,
+                                           bool newton, const Point<T, M>& z, Point<T, M>& d)
+{
+    cx<T> Sx[M], Sy[M];
+    eval_sums<T, M>(C, z, Sx, Sy);
+
+    const cx<T> g = omt * gamma;             // (1 - t) gamma
+    const cx<T> gt = {g.re + t, g.im};       // g + t
+    // -H = -(c1 Q + c2 F) with (c1, c2) = (g, t); -H_t = -(F - gamma Q), i.e.
+    // (c1, c2) = (-gamma, 1)
+    const cx<T> c1 = newton ? g : -gamma;
+    const T c2 = newton ? t : T(1);
+    cx<T> r[M], s[M];                        // right-hand side (gradient rows, constraints)
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        cx<T> xk = z.x[k], yk = z.y[k];
+        cx<T> F = yk * Sx[k] - xk * Sy[k];
+        cx<T> xx = xk * xk, yy = yk * yk;
+        cx<T> xm1 = {xx.re - T(1), xx.im};
+        cx<T> ym1 = {yy.re - T(1), yy.im};
+        cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
+        r[k] = -(c1 * xm1 + c2 * F);
+        s[k] = -(c1 * ym1 + c2 * con);
+    }
+
+    // constraint-row parametrisation
+    cx<T> a[M], b[M], px[M], py[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        a[k] = (T(2) * t) * z.x[k];
+        b[k] = T(2) * (gt * z.y[k]);
+        T nrm = norm2(a[k]) + norm2(b[k]);
+        T inv = T(1) / nrm;
+        cx<T> sk = s[k] * inv;
+        px[k] = sk * conj(a[k]);
+        py[k] = sk * conj(b[k]);
+    }
+
+    // reduced matrix R (row-major, registers) and right-hand side
+    cx<T> R[M][M];
+    cx<T> v[M];
+    {
+        const cx<T> sg = csqrt(gt);
+        const T st = sqrt(t);
+        cx<T> Xs[M], Ys[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            Xs[k] = st * z.x[k];
+            Ys[k] = sg * z.y[k];
+        }
+        const T two_t = T(2) * t;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+#pragma unroll
+            for (int j = k + 1; j < M; ++j) {
+                cx<T> e = Ys[j] * Ys[k] + Xs[j] * Xs[k];
+                cx<T> val = (two_t * C.J(k, j)) * e;
+                R[k][j] = val;
+                R[j][k] = val;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            cx<T> Akk = (T(2) * g) * z.x[k] - t * Sy[k];
+            cx<T> Bkk = t * Sx[k];
+            R[k][k] = Akk * b[k] - Bkk * a[k];
+            // sum_{j != k} (A_kj px_j + B_kj py_j) = t (y_k U_k - x_k W_k)
+            cx<T> U = {T(0), T(0)}, W = {T(0), T(0)};
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j == k) continue;
+                T Jkj = C.J(k, j);
+                U = U + Jkj * px[j];
+                W = W + Jkj * py[j];
+            }
+            cx<T> off = t * (z.y[k] * U - z.x[k] * W);
+            v[k] = r[k] - off - Akk * px[k] - Bkk * py[k];
+        }
+    }
+
+    // Gaussian elimination with partial pivoting, right-hand side attached.
+    bool ok = true;
+    cx<T> dinv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        T best = abs1(R[k][k]);
+        int p = k;
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            T m = abs1(R[i][k]);
+            bool bigger = m > best;
+            best = bigger ? m : best;
+            p = bigger ? i : p;
+        }
+        ok = ok && (best > T(0));
+        if (k + 1 < M) {
+            cx<T> rowk[M];
+            cx<T> vk = v[k];
+#pragma unroll
+            for (int j = k; j < M; ++j) rowk[j] = R[k][j];
+#pragma unroll
+            for (int i = k + 1; i < M; ++i) {
+                const bool sw = (p == i);
+#pragma unroll
+                for (int j = k; j < M; ++j) {
+                    cx<T> ri = R[i][j];
+                    R[k][j] = sel(sw, ri, R[k][j]);
+                    R[i][j] = sel(sw, rowk[j], ri);
+                }
+                cx<T> vi = v[i];
+                v[k] = sel(sw, vi, v[k]);
+                v[i] = sel(sw, vk, vi);
+            }
+        }
+        cx<T> inv = rcp(R[k][k]);
+        dinv[k] = inv;
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            cx<T> l = R[i][k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < M; ++j) R[i][j] = fnma(l, R[k][j], R[i][j]);
+            v[i] = fnma(l, v[k], v[i]);
+        }
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        cx<T> acc = v[i];
+#pragma unroll
+        for (int j = i + 1; j < M; ++j) acc = fnma(R[i][j], v[j], acc);
+        v[i] = acc * dinv[i];
+    }
+
+    // back to the full unknowns
+    T mag = T(0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        d.x[k] = fma(b[k], v[k], px[k]);
+        d.y[k] = fnma(a[k], v[k], py[k]);
+        mag = fmax(mag, fmax(absmax(d.x[k]), absmax(d.y[k])));
+    }
+    ok = ok && (mag - mag == T(0));  // false for inf and NaN
+    return ok;
+}
+
+// ||z||_inf in the max-of-|re|,|im| sense per coordinate (within sqrt(2) of
+// the modulus norm; used for the divergence radius and tolerances)
+template <class T, int M>
+__device__ __forceinline__ T norm_inf(const Point<T, M>& z)
+{
+    T r = T(0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) r = fmax(r, fmax(absmax(z.x[k]), absmax(z.y[k])));
+    return r;
+}
+
+}  // namespace nphc
