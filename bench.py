@@ -1,0 +1,196 @@
+#!/usr/bin/env python
+"""Benchmark: paths tracked per second on the clean power-law XY ring N=10
+(sigma = 1, h = 0, theta_N = 0: 18 complex unknowns, 4^9 = 262144 paths),
+float32 tracking with the float64 endgame, against the all-float64 pipeline.
+
+One step = the whole hot path on the GPU for all 262144 paths: track, refine
+and certify every endpoint, path-jump check, float64 re-tracking of failed or
+duplicated paths, real filter, Hessian-index classification, and the copy of
+the compact real stationary points to the host.  Inputs (couplings, gamma)
+are resident on the device before the timed region.
+
+Prints one JSON line.  Extra keys: the all-float64 rate and the speed-up, the
+tracking kernel's roofline (algorithmic flops per launch over the launch's
+duration, timed with HIP events on the launch stream), parity of the real
+stationary points with the oracle's stored result, and the CPU oracle timed on
+a sample of the same paths.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "paths tracked/s at N=10 (262144 paths), FP32+FP64-endgame vs all-FP64"
+N_RING, SIGMA, GAMMA_SEED = 10, 1.0, 0
+FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X vector fp32 (AMD spec)
+FP64_VECTOR_PEAK = 78.6    # TFLOP/s, MI355X vector fp64 (AMD spec)
+
+
+def fetch_real(b):
+    """Compact results to the host: counts, then the classified candidates."""
+    counts = b.counts.cpu()
+    K = int(counts[8])
+    return dict(K=K, is_real=b.is_real[:K].cpu(), index=b.index[:K].cpu(),
+                theta=b.theta[:, :K].cpu(), energy=b.energy[:K].cpu(),
+                degenerate=b.degenerate[:K].cpu())
+
+
+def time_pipeline(pipeline, batch, precision, steps, warmup):
+    import torch
+    opts = pipeline.Options(precision=precision)
+    bufs = pipeline.allocate(batch, precision)
+    for _ in range(warmup):
+        pipeline.run(batch, opts, bufs)
+        fetch_real(bufs)
+    torch.cuda.synchronize()
+    names = ("track_begin", "track_end", "resume_begin", "resume_end")
+    evs = [{k: torch.cuda.Event(enable_timing=True) for k in names} for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        pipeline.run(batch, opts, bufs, events=evs[k])
+        out = fetch_real(bufs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    track_ms = [e["track_begin"].elapsed_time(e["track_end"]) for e in evs]
+    resume_ms = ([e["resume_begin"].elapsed_time(e["resume_end"]) for e in evs]
+                 if precision == "fp32" else [0.0])
+    return (t1 - t0) / steps, track_ms, resume_ms, bufs, out
+
+
+def attribute_work(pipeline, batch, bufs, precision, m):
+    """Untimed run that splits the linear-solve count between the tracking
+    launch and the float64 continuation (the counter is cumulative per path)."""
+    import torch
+    from paper_1104_5497_amd import flops
+    snap = {}
+
+    def after_track():
+        snap["solves"] = bufs.solves.clone()
+        snap["steps"] = bufs.accepted + bufs.rejected
+
+    pipeline.run(batch, pipeline.Options(precision=precision), bufs,
+                 events={"track_begin": torch.cuda.Event(), "track_end": torch.cuda.Event(),
+                         "after_track": after_track})
+    torch.cuda.synchronize()
+    s1, st1 = int(snap["solves"].sum()), int(snap["steps"].sum())
+    # the continuation's counts: final minus snapshot on the handed-off paths
+    # (re-tracked paths restart their step counters and pass no solve counter)
+    s2 = int(bufs.solves.sum()) - s1
+    st2 = max(0, int((bufs.accepted + bufs.rejected).sum()) - st1)
+    return dict(track=flops.kernel_flops(m, s1, st1), track_solves=s1,
+                resume=flops.kernel_flops(m, s2, st2), resume_solves=s2)
+
+
+def parity_vs_golden(out, m):
+    """Compare the certified real stationary points with the oracle's stored
+    result (same count, same Hessian indices, angles within 1e-10 mod 2 pi)."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_ring10.json")
+    if not os.path.exists(path):
+        return None
+    from tests._match import match_sets
+    g = json.load(open(path))["rings"][0]
+    real = out["is_real"].numpy().astype(bool)
+    deg = out["degenerate"].numpy().astype(bool)[real]
+    th = out["theta"].numpy()[:m].T[real][~deg]
+    idx = out["index"].numpy()[real][~deg]
+    hist = np.bincount(idx, minlength=m).tolist()
+    try:
+        err = match_sets(th, idx, np.array(g["theta"]), np.array(g["index"]))
+        ok = True
+    except AssertionError:
+        err, ok = None, False
+    return dict(num_real=int(th.shape[0]), oracle_num_real=g["num_real"], histogram=hist,
+                oracle_histogram=g["histogram"], sets_equal=ok, max_theta_err=err)
+
+
+def cpu_baseline(J, gamma, sample, seed=1):
+    """The oracle as it stands (track + refine) on a random sample of path ids."""
+    import oracle
+    threads = min(16, len(os.sched_getaffinity(0)))
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(4 ** (N_RING - 1), size=sample, replace=False)).astype(np.int64)
+    s = oracle.System(J)
+    t0 = time.perf_counter()
+    r = s.track(gamma, ids, oracle.TrackOpts(), nthreads=threads)
+    fin = (r["status"] == oracle.ST_REACHED)
+    s.refine(r["z"][fin])
+    dt = time.perf_counter() - t0
+    return dict(value=sample / dt, unit="paths/s", cores=threads, kind="oracle",
+                sample=f"{sample} random path ids of the N=10 ring (seed {seed}), "
+                       f"tracked and refined with the oracle's FP64 C tracker on {threads} threads; "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the path set would shard by path id across GPUs, "
+              "but this build measures a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workload
+    from paper_1104_5497_amd import flops, pipeline
+
+    J = workload.clean_ring_J(N_RING, SIGMA)
+    gamma = workload.gamma_from_seed(GAMMA_SEED)
+    m = N_RING - 1
+    P = 4 ** m
+    batch = pipeline.Batch([J], [gamma], "cuda")
+
+    sec32, tr32, rs32, b32, out32 = time_pipeline(pipeline, batch, "fp32", a.steps, a.warmup)
+    w32 = attribute_work(pipeline, batch, b32, "fp32", m)
+    k_track = dict(kernel="nphc::track_uniform_kernel<float, 9>", dtype="f32",
+                   launch_ms=float(np.mean(tr32)), flops=w32["track"], solves=w32["track_solves"],
+                   peak=FP32_VECTOR_PEAK)
+    k_resume = dict(kernel="nphc::track_uniform_kernel<double, 9> (continuation)", dtype="f64",
+                    launch_ms=float(np.mean(rs32)), flops=w32["resume"],
+                    solves=w32["resume_solves"], peak=FP64_VECTOR_PEAK)
+    for k in (k_track, k_resume):
+        k["achieved"] = k["flops"] / (k["launch_ms"] / 1e3) / 1e12 if k["launch_ms"] > 0 else 0.0
+        k["frac"] = k["achieved"] / k["peak"]
+    dom = max((k_track, k_resume), key=lambda k: k["launch_ms"])
+    parity = parity_vs_golden(out32, m)
+
+    res = dict(metric=METRIC, value=P / sec32, unit="paths/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=sec32 * 1e3, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32+f64", data="synthetic",
+               config=dict(workload="clean XY ring N=10 sigma=1 h=0, 262144 total-degree paths, "
+                                    "FP32 track + FP64 continuation/endgame/re-track/certify/classify",
+                           N=N_RING, sigma=SIGMA, gamma_seed=GAMMA_SEED, paths=P),
+               roofline=dict(bound="alu", achieved=dom["achieved"], peak=dom["peak"],
+                             unit="TFLOP/s", frac=dom["frac"], traffic=None,
+                             kernel=dom["kernel"], launch_ms=dom["launch_ms"],
+                             flops_per_launch=dom["flops"], solve_flops=flops.solve_flops(m),
+                             dense_equiv_flops=dom["solves"] * flops.dense_solve_flops(m)),
+               kernels=[k_track, k_resume],
+               parity=parity)
+    if not a.no_fp64:
+        sec64, tr64, _, b64, out64 = time_pipeline(pipeline, batch, "fp64", a.steps, a.warmup)
+        w64 = attribute_work(pipeline, batch, b64, "fp64", m)
+        ach64 = w64["track"] / (np.mean(tr64) / 1e3) / 1e12
+        res["fp64"] = dict(value=P / sec64, ms_per_step=sec64 * 1e3,
+                           track_ms=float(np.mean(tr64)), achieved_tflops=ach64,
+                           frac_of_fp64_peak=ach64 / FP64_VECTOR_PEAK,
+                           parity=parity_vs_golden(out64, m))
+        res["speedup_vs_fp64"] = sec64 / sec32
+    if not a.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(J, gamma, a.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,6 +75,7 @@ extern "C" {
 #define NPHC_PATH_FAIL_MAXSTEPS 4
 #define NPHC_PATH_FAIL_NONFINITE 5
 #define NPHC_PATH_STALLED 6        /* step size fell below h_min at t >= t_stall */
+#define NPHC_PATH_HANDOFF 7        /* stopped for a float64 continuation (z, t, h saved) */
 
 /* per-item endpoint classes written by nphc_refine_certify / nphc_mark_duplicates */
 #define NPHC_END_NONSINGULAR 10
@@ -113,7 +114,26 @@ typedef struct nphc_track_opts {
     int32_t max_corr; /* Newton iterations per step */
     int32_t max_steps;/* accepted + rejected steps */
     int32_t predictor;/* 0: classical RK4, 1: Euler (the paper's predictor) */
+    int32_t resume;   /* 1: continue each selected path from its saved z, t, h and step counts */
+    double handoff_norm;     /* > 0: stop a path with NPHC_PATH_HANDOFF once ||z||_inf > handoff_norm */
+    int32_t handoff_rejects; /* > 0: stop with NPHC_PATH_HANDOFF after this many rejected steps
+                                in a row, or when the step size collapses */
     int32_t pad;
+    /* end zone t >= t_endzone (near t = 1):
+     *  - after an accepted step that grew ||z||_inf by more than grow_ratio,
+     *    the next step is at most grow_cap (1 - t) (the path is heading to
+     *    infinity: no attempt to finish at t_end);
+     *  - a step below hmin_rel (1 - t) while ||z||_inf > collapse_norm is a
+     *    collapse, like a step below hmin.
+     * grow_cap = 0 or hmin_rel = 0 disables the rule. */
+    double t_endzone;
+    double hmin_rel;
+    double collapse_norm;
+    double grow_ratio;
+    double grow_cap;
+    int32_t grid_blocks;     /* persistent grid size in 64-lane workgroups (0: one per resident wave slot) */
+    int32_t handoff_steps;   /* > 0: stop with NPHC_PATH_HANDOFF after this many steps (bounds the
+                                float32 work of paths that creep through ill-conditioned stretches) */
 } nphc_track_opts;
 
 /* Endpoint refinement and certification settings. */
@@ -153,15 +173,22 @@ size_t nphc_track_workspace_size(const nphc_batch* b, int precision);
  * persistent launch per call; each GPU lane tracks one path at a time and
  * takes the next queued item when its path ends.  precision NPHC_FP32 does
  * the predictor/corrector arithmetic in complex float32 (t and h stay
+ * float64).  With handoff_rejects > 0 a path whose step size collapses (or
+ * that is rejected that many times in a row) stops with NPHC_PATH_HANDOFF and
+ * its state is saved; a later call with resume = 1 continues it (normally in
  * float64).
  * Outputs (device, per item, only the selected items are written): z
  * (endpoint, planes as above), t (final t), status (NPHC_PATH_*), accepted
- * and rejected step counts.
+ * and rejected step counts, (if solves is not NULL) the number of linear
+ * solves the path took (predictor stages plus corrector iterations), and (if
+ * h is not NULL) the step size to continue with.  With resume = 1, z, t, h,
+ * accepted, rejected and solves (when given) are also read as the start
+ * state; h must then be given.
  */
 int nphc_track_paths(const nphc_batch* b, const int64_t* ids, int64_t count,
                      const int64_t* count_dev, int precision, const nphc_track_opts* o,
                      double* z, int64_t item_stride, double* t, int32_t* status,
-                     int32_t* accepted, int32_t* rejected,
+                     int32_t* accepted, int32_t* rejected, int32_t* solves, double* h,
                      void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /*

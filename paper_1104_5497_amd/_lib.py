@@ -18,7 +18,7 @@ NPHC_OK, NPHC_EINVAL, NPHC_EUNSUPPORTED, NPHC_EHIP, NPHC_EWORKSPACE = 0, -1, -2,
 NPHC_FP64, NPHC_FP32 = 0, 1
 
 PATH_PENDING, PATH_REACHED, PATH_DIVERGED, PATH_FAIL_MINSTEP = 0, 1, 2, 3
-PATH_FAIL_MAXSTEPS, PATH_FAIL_NONFINITE, PATH_STALLED = 4, 5, 6
+PATH_FAIL_MAXSTEPS, PATH_FAIL_NONFINITE, PATH_STALLED, PATH_HANDOFF = 4, 5, 6, 7
 END_NONSINGULAR, END_SINGULAR, END_DIVERGED, END_FAIL, END_DUPLICATE = 10, 11, 12, 13, 14
 
 EXPORTS = [
@@ -45,7 +45,19 @@ class TrackOpts_(ctypes.Structure):
                 ("corr_tol", ctypes.c_double), ("R_inf", ctypes.c_double),
                 ("t_stall", ctypes.c_double), ("t_end", ctypes.c_double),
                 ("max_corr", ctypes.c_int32), ("max_steps", ctypes.c_int32),
-                ("predictor", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("predictor", ctypes.c_int32), ("resume", ctypes.c_int32),
+                ("handoff_norm", ctypes.c_double), ("handoff_rejects", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("t_endzone", ctypes.c_double),
+                ("hmin_rel", ctypes.c_double), ("collapse_norm", ctypes.c_double),
+                ("grow_ratio", ctypes.c_double), ("grow_cap", ctypes.c_double),
+                ("grid_blocks", ctypes.c_int32), ("handoff_steps", ctypes.c_int32)]
+
+    def copy(self, **kw) -> "TrackOpts_":
+        o = TrackOpts_()
+        ctypes.pointer(o)[0] = self
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
 
 
 class CertOpts_(ctypes.Structure):
@@ -83,7 +95,7 @@ def lib() -> ctypes.CDLL:
     L.nphc_track_workspace_size.argtypes = [pB, i32]
     L.nphc_track_workspace_size.restype = sz
     L.nphc_track_paths.argtypes = [pB, vp, i64, vp, i32, ctypes.POINTER(TrackOpts_), vp, i64, vp,
-                                   vp, vp, vp, vp, sz, vp]
+                                   vp, vp, vp, vp, vp, vp, sz, vp]
     L.nphc_refine_certify.argtypes = [pB, vp, i64, vp, ctypes.POINTER(CertOpts_), vp, i64, vp, vp,
                                       vp, vp, vp, vp, vp, vp, vp]
     L.nphc_mark_duplicates.argtypes = [pB, vp, i64, vp, dbl, vp, i64, vp, vp, vp, sz, vp]

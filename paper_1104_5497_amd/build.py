@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnphc.so")
 SOURCES = ["api.hip", "track.hip", "refine.hip", "select.hip", "classify.hip", "adjoint.hip"]
-HEADERS = ["cx.hpp", "xy_lane.hpp", "xy_dense.hpp", "wave_dense.hpp", "common.hpp"]
+HEADERS = ["cx.hpp", "xy_lane.hpp", "path.hpp", "xy_dense.hpp", "wave_dense.hpp", "common.hpp"]
 ARCH = os.environ.get("NPHC_OFFLOAD_ARCH", "gfx950")
 
 # packed-fp32 instructions are disabled for every HIP source of this library

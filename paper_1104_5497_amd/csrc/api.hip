@@ -37,14 +37,26 @@ extern "C" void nphc_default_track_opts(int precision, nphc_track_opts* o)
     o->h0 = 0.01;
     o->hmax = 0.05;
     o->hmin = 1e-13;
-    o->corr_tol = precision == NPHC_FP32 ? 1e-5 : 1e-10;
-    o->R_inf = precision == NPHC_FP32 ? 1e5 : 1e8;
+    // tracking tolerance: float32 runs at its precision; float64 tracking
+    // does not need more than 1e-8 since every endpoint is refined to 1e-15
+    o->corr_tol = precision == NPHC_FP32 ? 1e-5 : 1e-8;
+    o->R_inf = 1e5;
     o->t_stall = 1.0 - 1e-6;
     o->t_end = 1.0;
     o->max_corr = 3;
     o->max_steps = 20000;
     o->predictor = 0;
+    o->resume = 0;
+    o->handoff_norm = 0.0;
+    o->handoff_rejects = precision == NPHC_FP32 ? 4 : 0;
     o->pad = 0;
+    o->t_endzone = 0.9;
+    o->hmin_rel = 1e-3;
+    o->collapse_norm = 1e4;
+    o->grow_ratio = 1.25;
+    o->grow_cap = 0.5;
+    o->grid_blocks = 0;
+    o->handoff_steps = precision == NPHC_FP32 ? 160 : 0;
 }
 
 extern "C" void nphc_default_cert_opts(nphc_cert_opts* o)

@@ -26,7 +26,17 @@ struct QueueState {
 
 struct TrackOptsDev {
     double h0, hmax, hmin, corr_tol, R_inf, t_stall, t_end;
-    int32_t max_corr, max_steps, predictor, pad;
+    int32_t max_corr, max_steps, predictor, resume;
+    double handoff_norm;       // > 0: stop with HANDOFF once ||z|| exceeds it
+    int32_t handoff_rejects;   // > 0: stop with HANDOFF after this many rejections in a row
+    int32_t pad;
+    double t_endzone;          // end zone: t >= t_endzone
+    double hmin_rel;           // end zone: a step below hmin_rel (1 - t) with ||z|| > collapse_norm is a collapse
+    double collapse_norm;
+    double grow_ratio;         // end zone: ||z|| grew by this factor over the last step ...
+    double grow_cap;           // ... then the next step is at most grow_cap (1 - t)
+    int32_t handoff_steps;     // > 0: stop with HANDOFF after this many steps
+    int32_t pad2;
 };
 
 struct TrackArgs {
@@ -50,6 +60,8 @@ struct TrackArgs {
     int32_t* status;
     int32_t* accepted;
     int32_t* rejected;
+    int32_t* solves;           // nullable
+    double* h;                 // nullable (required with o.resume)
 };
 
 __device__ __forceinline__ int64_t find_system(const int64_t* path_off, int32_t num_systems,

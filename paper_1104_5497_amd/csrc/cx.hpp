@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#ifndef NPHC_HD
+#define NPHC_HD __host__ __device__ __forceinline__
+#endif
+
 namespace nphc {
 
 template <class T>
@@ -38,14 +42,43 @@ template <class T> __host__ __device__ __forceinline__ cx<T> fma(cx<T> a, cx<T> 
     return {c.re + a.re * b.re - a.im * b.im, c.im + a.re * b.im + a.im * b.re};
 }
 
+// y + a x for a real scalar a
+template <class T> __host__ __device__ __forceinline__ cx<T> axpy(T a, cx<T> x, cx<T> y)
+{
+    return {y.re + a * x.re, y.im + a * x.im};
+}
+
+// Reciprocal of a real number: the hardware reciprocal (1 ulp) in float32;
+// in float64 the hardware estimate refined by two Newton steps.
+__host__ __device__ __forceinline__ float rrcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ double rrcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
 // 1 / a, scaled by the larger component so that |a|^2 neither overflows nor
 // underflows for any finite nonzero a.
 template <class T> __host__ __device__ __forceinline__ cx<T> rcp(cx<T> a)
 {
     T s = absmax(a);
-    T inv_s = T(1) / s;
+    T inv_s = rrcp(s);
     T ar = a.re * inv_s, ai = a.im * inv_s;
-    T d = T(1) / ((ar * ar + ai * ai) * s);
+    T d = rrcp((ar * ar + ai * ai) * s);
     return {ar * d, -ai * d};
 }
 

@@ -1,0 +1,147 @@
+// path.hpp -- one path's state and one predictor-corrector step (per lane;
+// also compiles for the host).
+#pragma once
+#include "common.hpp"
+#include "xy_lane.hpp"
+
+namespace nphc {
+
+template <class T, int M>
+struct LanePath {
+    Point<T, M> z;
+    double t, h;
+    double h_acc;       // step size of the last accepted step
+    double znorm;       // ||z|| after the last accepted step
+    int32_t streak, acc, rej, status, solves, rej_run;
+};
+
+template <class T, int M>
+NPHC_HD void start_point(int64_t pid, Point<T, M>& z)
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        z.x[k] = {((pid >> k) & 1) ? T(-1) : T(1), T(0)};
+        z.y[k] = {((pid >> (M + k)) & 1) ? T(-1) : T(1), T(0)};
+    }
+}
+
+// One predictor-corrector step of one lane's path (paper, section "NPHC
+// method": predictor, then Newton's corrector; step control as documented in
+// nphc_track_paths).  Sets S.status when the path ends.
+template <class T, int M>
+NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
+                                          const TrackOptsDev& o, LanePath<T, M>& S)
+{
+    const bool last = S.h >= o.t_end - S.t;
+    const double hh = last ? (o.t_end - S.t) : S.h;
+    const double t1 = last ? o.t_end : S.t + hh;
+    const int nst = o.predictor == 0 ? 4 : 1;
+
+    Point<T, M> zq = S.z;  // where the next linear solve is evaluated
+    Point<T, M> w;         // RK4 accumulator, then the corrected point
+    bool ok = true, conv = false, bad = false;
+    T prev = T(0);
+
+    for (int s = 0; s < nst + o.max_corr; ++s) {
+        const bool pred = s < nst;
+        const bool want = pred ? ok : (ok && !conv && !bad);
+        if (!want) continue;
+        // stage times of the classical RK4: t, t + h/2, t + h/2, t + h
+        const double tq = !pred ? t1 : (s == 0 ? S.t : (s == 3 ? t1 : S.t + 0.5 * hh));
+        Point<T, M> d;
+        const bool sok = solve_step<T, M>(C, gamma, T(tq), T(1.0 - tq), !pred, zq, d);
+        S.solves += 1;
+        if (pred) {
+            ok = ok && sok;
+            const T ws = (s == 0 || s == 3) ? T(1) : T(2);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                w.x[i] = (s == 0) ? d.x[i] : axpy(ws, d.x[i], w.x[i]);
+                w.y[i] = (s == 0) ? d.y[i] : axpy(ws, d.y[i], w.y[i]);
+            }
+            if (s < nst - 1) {
+                const T ch = T((s == 2 ? 1.0 : 0.5) * hh);  // next stage point
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    zq.x[i] = axpy(ch, d.x[i], S.z.x[i]);
+                    zq.y[i] = axpy(ch, d.y[i], S.z.y[i]);
+                }
+            } else {
+                const T f = T(nst == 4 ? hh / 6.0 : hh);
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    w.x[i] = axpy(f, w.x[i], S.z.x[i]);
+                    w.y[i] = axpy(f, w.y[i], S.z.y[i]);
+                }
+                zq = w;
+            }
+        } else {
+            if (!sok) {
+                bad = true;
+            } else {
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    w.x[i] = w.x[i] + d.x[i];
+                    w.y[i] = w.y[i] + d.y[i];
+                }
+                zq = w;
+                const T nd = norm_inf<T, M>(d);
+                if (s > nst && nd > T(0.5) * prev) bad = true;
+                prev = nd;
+                if (!bad && nd <= T(o.corr_tol) * (T(1) + norm_inf<T, M>(w))) conv = true;
+            }
+        }
+    }
+
+    const T wn = norm_inf<T, M>(w);
+    const bool finite = (wn - wn == T(0));
+    if (ok && conv && !bad && !finite) {
+        S.status = NPHC_PATH_FAIL_NONFINITE;
+        return;
+    }
+    if (ok && conv && !bad) {
+        S.z = w;
+        S.t = t1;
+        S.acc += 1;
+        S.h_acc = hh;
+        S.rej_run = 0;
+        if (++S.streak == 3) {
+            S.h = fmin(2.0 * hh, o.hmax);
+            S.streak = 0;
+        } else {
+            S.h = hh;
+        }
+        // end zone: while ||z|| keeps growing the path is heading to infinity;
+        // step a fixed fraction of the remaining distance instead of trying to
+        // finish at t_end
+        if (S.t >= o.t_endzone && o.grow_cap > 0.0 && double(wn) > o.grow_ratio * S.znorm)
+            S.h = fmin(S.h, o.grow_cap * (o.t_end - S.t));
+        S.znorm = double(wn);
+        if (double(wn) > o.R_inf) S.status = NPHC_PATH_DIVERGED;
+        else if (S.t >= o.t_end) S.status = NPHC_PATH_REACHED;
+        else if (o.handoff_norm > 0.0 && double(wn) > o.handoff_norm) S.status = NPHC_PATH_HANDOFF;
+    } else {
+        S.rej += 1;
+        S.rej_run += 1;
+        S.streak = 0;
+        S.h = 0.5 * hh;
+        // near t = 1 a step far below the remaining distance 1 - t means the
+        // path is heading to infinity or to a singular endpoint
+        const bool collapse = S.h < o.hmin ||
+                              (S.t >= o.t_endzone && S.h < o.hmin_rel * (o.t_end - S.t) &&
+                               S.znorm > o.collapse_norm);
+        if (o.handoff_rejects > 0 && S.rej_run >= o.handoff_rejects) {
+            S.status = NPHC_PATH_HANDOFF;
+        } else if (collapse) {
+            S.status = o.handoff_rejects > 0 ? NPHC_PATH_HANDOFF
+                       : (S.t >= o.t_stall) ? NPHC_PATH_STALLED : NPHC_PATH_FAIL_MINSTEP;
+        }
+    }
+    if (S.status == NPHC_PATH_PENDING && o.handoff_steps > 0 && S.acc + S.rej >= o.handoff_steps)
+        S.status = NPHC_PATH_HANDOFF;
+    if (S.status == NPHC_PATH_HANDOFF) S.h = S.h_acc;  // the continuation restarts from here
+    if (S.status == NPHC_PATH_PENDING && S.acc + S.rej >= o.max_steps)
+        S.status = NPHC_PATH_FAIL_MAXSTEPS;
+}
+
+}  // namespace nphc

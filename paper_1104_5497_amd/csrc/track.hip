@@ -9,126 +9,9 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
-#include "xy_lane.hpp"
+#include "path.hpp"
 
 namespace nphc {
-
-template <class T, int M>
-struct LanePath {
-    Point<T, M> z;
-    double t, h;
-    int32_t streak, acc, rej, status;
-};
-
-template <class T, int M>
-__device__ __forceinline__ void start_point(int64_t pid, Point<T, M>& z)
-{
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        z.x[k] = {((pid >> k) & 1) ? T(-1) : T(1), T(0)};
-        z.y[k] = {((pid >> (M + k)) & 1) ? T(-1) : T(1), T(0)};
-    }
-}
-
-// One predictor-corrector step of one lane's path (paper, section "NPHC
-// method": predictor, then Newton's corrector; step control as documented in
-// nphc_track_paths).  Sets S.status when the path ends.
-template <class T, int M>
-__device__ __forceinline__ void path_step(const Couplings<T, M>& C, cx<T> gamma,
-                                          const TrackOptsDev& o, LanePath<T, M>& S)
-{
-    const bool last = S.h >= o.t_end - S.t;
-    const double hh = last ? (o.t_end - S.t) : S.h;
-    const double t1 = last ? o.t_end : S.t + hh;
-    const int nst = o.predictor == 0 ? 4 : 1;
-
-    Point<T, M> k;   // previous stage's tangent
-    Point<T, M> w;   // RK4 accumulator, then the corrected point
-    bool ok = true, conv = false, bad = false;
-    T prev = T(0);
-
-    for (int s = 0; s < nst + o.max_corr; ++s) {
-        const bool pred = s < nst;
-        const bool want = pred ? ok : (ok && !conv && !bad);
-        if (!want) continue;
-        // evaluation point and time
-        double cs = 0.0;
-        if (pred) cs = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
-        const double tq = pred ? (s == 3 ? t1 : S.t + cs * hh) : t1;
-        Point<T, M> zq;
-        if (pred) {
-            const T ch = T(cs * hh);
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                zq.x[i] = (s == 0) ? S.z.x[i] : fma(mk(ch, T(0)), k.x[i], S.z.x[i]);
-                zq.y[i] = (s == 0) ? S.z.y[i] : fma(mk(ch, T(0)), k.y[i], S.z.y[i]);
-            }
-        } else {
-            zq = w;
-        }
-        Point<T, M> d;
-        const bool sok = solve_step<T, M>(C, gamma, T(tq), T(1.0 - tq), !pred, zq, d);
-        if (pred) {
-            ok = ok && sok;
-            const T ws = (s == 0 || s == 3) ? T(1) : T(2);
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                w.x[i] = (s == 0) ? d.x[i] : fma(mk(ws, T(0)), d.x[i], w.x[i]);
-                w.y[i] = (s == 0) ? d.y[i] : fma(mk(ws, T(0)), d.y[i], w.y[i]);
-            }
-            k = d;
-            if (s == nst - 1) {
-                const T f = T(nst == 4 ? hh / 6.0 : hh);
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    w.x[i] = fma(mk(f, T(0)), w.x[i], S.z.x[i]);
-                    w.y[i] = fma(mk(f, T(0)), w.y[i], S.z.y[i]);
-                }
-            }
-        } else {
-            if (!sok) {
-                bad = true;
-            } else {
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    w.x[i] = w.x[i] + d.x[i];
-                    w.y[i] = w.y[i] + d.y[i];
-                }
-                const T nd = norm_inf<T, M>(d);
-                if (s > nst && nd > T(0.5) * prev) bad = true;
-                prev = nd;
-                if (!bad && nd <= T(o.corr_tol) * (T(1) + norm_inf<T, M>(w))) conv = true;
-            }
-        }
-    }
-
-    const T wn = norm_inf<T, M>(w);
-    const bool finite = (wn - wn == T(0));
-    if (ok && conv && !bad && !finite) {
-        S.status = NPHC_PATH_FAIL_NONFINITE;
-        return;
-    }
-    if (ok && conv && !bad) {
-        S.z = w;
-        S.t = t1;
-        S.acc += 1;
-        if (++S.streak == 3) {
-            S.h = fmin(2.0 * (last ? hh : S.h), o.hmax);
-            S.streak = 0;
-        } else if (last) {
-            S.h = hh;
-        }
-        if (double(wn) > o.R_inf) S.status = NPHC_PATH_DIVERGED;
-        else if (S.t >= o.t_end) S.status = NPHC_PATH_REACHED;
-    } else {
-        S.rej += 1;
-        S.streak = 0;
-        S.h = 0.5 * hh;
-        if (S.h < o.hmin) S.status = (S.t >= o.t_stall) ? NPHC_PATH_STALLED : NPHC_PATH_FAIL_MINSTEP;
-    }
-    if (S.status == NPHC_PATH_PENDING && S.acc + S.rej >= o.max_steps)
-        S.status = NPHC_PATH_FAIL_MAXSTEPS;
-}
 
 template <class T, int M>
 __device__ __forceinline__ void write_path(const TrackArgs& A, int64_t item, const LanePath<T, M>& S)
@@ -145,6 +28,24 @@ __device__ __forceinline__ void write_path(const TrackArgs& A, int64_t item, con
     A.status[item] = S.status;
     A.accepted[item] = S.acc;
     A.rejected[item] = S.rej;
+    if (A.solves) A.solves[item] = S.solves;
+    if (A.h) A.h[item] = S.h;
+}
+
+template <class T, int M>
+__device__ __forceinline__ void read_path(const TrackArgs& A, int64_t item, LanePath<T, M>& S)
+{
+    const int64_t st = A.out_stride;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        S.z.x[k] = {T(A.z[(2 * k) * st + item]), T(A.z[(2 * k + 1) * st + item])};
+        S.z.y[k] = {T(A.z[(2 * (M + k)) * st + item]), T(A.z[(2 * (M + k) + 1) * st + item])};
+    }
+    S.t = A.t[item];
+    S.h = A.h[item];
+    S.acc = A.accepted[item];
+    S.rej = A.rejected[item];
+    S.solves = A.solves ? A.solves[item] : 0;
 }
 
 // Process every queue position of class c.  UNIFORM: the batch has a single
@@ -190,10 +91,17 @@ __device__ void run_class(const TrackArgs& A, int c)
                             C.p = reinterpret_cast<const T*>(A.Jpack) + A.Jpack_off[sys];
                             gamma = {T(A.gamma[2 * sys]), T(A.gamma[2 * sys + 1])};
                         }
-                        start_point<T, M>(pid, S.z);
-                        S.t = 0.0;
-                        S.h = A.o.h0;
-                        S.streak = S.acc = S.rej = 0;
+                        if (A.o.resume) {
+                            read_path<T, M>(A, item, S);
+                        } else {
+                            start_point<T, M>(pid, S.z);
+                            S.t = 0.0;
+                            S.h = A.o.h0;
+                            S.acc = S.rej = S.solves = 0;
+                        }
+                        S.h_acc = S.h;
+                        S.znorm = double(norm_inf<T, M>(S.z));
+                        S.streak = S.rej_run = 0;
                         S.status = NPHC_PATH_PENDING;
                         active = true;
                     }
@@ -325,8 +233,8 @@ template <class T>
 static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
                         const int64_t* count_dev, const nphc_track_opts* o, double* z,
                         int64_t item_stride, double* t, int32_t* status, int32_t* accepted,
-                        int32_t* rejected, void* ws, size_t ws_bytes, hipStream_t stream,
-                        int precision)
+                        int32_t* rejected, int32_t* solves, double* h, void* ws,
+                        size_t ws_bytes, hipStream_t stream, int precision)
 {
     bool mixed;
     int minN, maxN;
@@ -352,14 +260,34 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     A.Jpack_off = reinterpret_cast<const int64_t*>(base + L.jpo_off);
     A.ids = ids;
     A.q = reinterpret_cast<QueueState*>(base + L.q_off);
-    A.o = {o->h0, o->hmax, o->hmin, o->corr_tol, o->R_inf, o->t_stall, o->t_end,
-           o->max_corr, o->max_steps, o->predictor, 0};
+    A.o.h0 = o->h0;
+    A.o.hmax = o->hmax;
+    A.o.hmin = o->hmin;
+    A.o.corr_tol = o->corr_tol;
+    A.o.R_inf = o->R_inf;
+    A.o.t_stall = o->t_stall;
+    A.o.t_end = o->t_end;
+    A.o.max_corr = o->max_corr;
+    A.o.max_steps = o->max_steps;
+    A.o.predictor = o->predictor;
+    A.o.resume = o->resume;
+    A.o.handoff_norm = o->handoff_norm;
+    A.o.handoff_rejects = o->handoff_rejects;
+    A.o.t_endzone = o->t_endzone;
+    A.o.hmin_rel = o->hmin_rel;
+    A.o.collapse_norm = o->collapse_norm;
+    A.o.grow_ratio = o->grow_ratio;
+    A.o.grow_cap = o->grow_cap;
+    A.o.handoff_steps = o->handoff_steps;
     A.out_stride = item_stride;
     A.z = z;
     A.t = t;
     A.status = status;
     A.accepted = accepted;
     A.rejected = rejected;
+    A.solves = solves;
+    A.h = h;
+    if (o->resume && !h) return NPHC_EINVAL;
     // classes: maximal runs of equal N (systems are sorted by N)
     int nc = 0;
     for (int s = 0; s < b->num_systems; ++s) {
@@ -404,7 +332,7 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const int grid = cus * per_cu;
+    const int grid = o->grid_blocks > 0 ? o->grid_blocks : cus * per_cu;
     void* args[] = {&A};
     if (hipLaunchKernel(fn, dim3(grid), dim3(64), args, 0, stream) != hipSuccess) return NPHC_EHIP;
     if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
@@ -422,14 +350,16 @@ extern "C" size_t nphc_track_workspace_size(const nphc_batch* b, int precision)
 extern "C" int nphc_track_paths(const nphc_batch* b, const int64_t* ids, int64_t count,
                                 const int64_t* count_dev, int precision, const nphc_track_opts* o,
                                 double* z, int64_t item_stride, double* t, int32_t* status,
-                                int32_t* accepted, int32_t* rejected, void* workspace,
-                                size_t ws_bytes, hipStream_t stream)
+                                int32_t* accepted, int32_t* rejected, int32_t* solves,
+                                double* h, void* workspace, size_t ws_bytes, hipStream_t stream)
 {
     if (precision == NPHC_FP64)
         return nphc::launch_track<double>(b, ids, count, count_dev, o, z, item_stride, t, status,
-                                          accepted, rejected, workspace, ws_bytes, stream, precision);
+                                          accepted, rejected, solves, h, workspace, ws_bytes, stream,
+                                          precision);
     if (precision == NPHC_FP32)
         return nphc::launch_track<float>(b, ids, count, count_dev, o, z, item_stride, t, status,
-                                         accepted, rejected, workspace, ws_bytes, stream, precision);
+                                         accepted, rejected, solves, h, workspace, ws_bytes, stream,
+                                         precision);
     return NPHC_EUNSUPPORTED;
 }

@@ -36,8 +36,8 @@ namespace nphc {
 template <class T, int M>
 struct Couplings {
     const T* p;
-    __device__ __forceinline__ T J(int k, int j) const { return p[k * M + j]; }
-    __device__ __forceinline__ T w(int k) const { return p[M * M + k]; }
+    NPHC_HD T J(int k, int j) const { return p[k * M + j]; }
+    NPHC_HD T w(int k) const { return p[M * M + k]; }
 };
 
 template <class T, int M>
@@ -47,7 +47,7 @@ struct Point {
 
 // Sx, Sy and F at z.
 template <class T, int M>
-__device__ __forceinline__ void eval_sums(const Couplings<T, M>& C, const Point<T, M>& z,
+NPHC_HD void eval_sums(const Couplings<T, M>& C, const Point<T, M>& z,
                                           cx<T> Sx[M], cx<T> Sy[M])
 {
 #pragma unroll
@@ -72,7 +72,7 @@ __device__ __forceinline__ void eval_sums(const Couplings<T, M>& C, const Point<
 // omt = 1 - t (passed separately so that it keeps its relative precision near
 // t = 1).  Returns false when a pivot vanishes or the result is not finite.
 template <class T, int M>
-__device__ __forceinline__ bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt,
+NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt,
                                            bool newton, const Point<T, M>& z, Point<T, M>& d)
 {
     cx<T> Sx[M], Sy[M];
@@ -104,7 +104,7 @@ __device__ __forceinline__ bool solve_step(const Couplings<T, M>& C, cx<T> gamma
         a[k] = (T(2) * t) * z.x[k];
         b[k] = T(2) * (gt * z.y[k]);
         T nrm = norm2(a[k]) + norm2(b[k]);
-        T inv = T(1) / nrm;
+        T inv = rrcp(nrm);
         cx<T> sk = s[k] * inv;
         px[k] = sk * conj(a[k]);
         py[k] = sk * conj(b[k]);
@@ -219,7 +219,7 @@ __device__ __forceinline__ bool solve_step(const Couplings<T, M>& C, cx<T> gamma
 // ||z||_inf in the max-of-|re|,|im| sense per coordinate (within sqrt(2) of
 // the modulus norm; used for the divergence radius and tolerances)
 template <class T, int M>
-__device__ __forceinline__ T norm_inf(const Point<T, M>& z)
+NPHC_HD T norm_inf(const Point<T, M>& z)
 {
     T r = T(0);
 #pragma unroll

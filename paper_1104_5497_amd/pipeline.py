@@ -97,6 +97,8 @@ class Buffers:
     status: torch.Tensor
     accepted: torch.Tensor
     rejected: torch.Tensor
+    solves: torch.Tensor
+    h: torch.Tensor
     endpoint: torch.Tensor
     resid: torch.Tensor
     cond: torch.Tensor
@@ -128,7 +130,8 @@ def allocate(batch: Batch, precision: str) -> Buffers:
     return Buffers(
         z=torch.zeros((2 * n, P), **f64), t=torch.zeros(P, **f64),
         status=torch.zeros(P, **i32), accepted=torch.zeros(P, **i32),
-        rejected=torch.zeros(P, **i32), endpoint=torch.zeros(P, **i32),
+        rejected=torch.zeros(P, **i32), solves=torch.zeros(P, **i32), h=torch.zeros(P, **f64),
+        endpoint=torch.zeros(P, **i32),
         resid=torch.zeros(P, **f64), cond=torch.zeros(P, **f64), beta=torch.zeros(P, **f64),
         alpha=torch.zeros(P, **f64), alpha_real=torch.zeros(P, **f64),
         ids=torch.zeros(P, **i64), ids2=torch.zeros(P, **i64), counts=torch.zeros(16, **i64),
@@ -150,16 +153,28 @@ def _mask(*codes: int) -> int:
 class Options:
     precision: str = "fp32"
     track: Optional[L.TrackOpts_] = None        # defaults per precision
+    resume: Optional[L.TrackOpts_] = None       # float64 continuation of handed-off paths
     retrack: Optional[L.TrackOpts_] = None      # float64 re-tracking (hmax divided by 4 per round)
     cert: Optional[L.CertOpts_] = None
     classify: Optional[L.ClassOpts_] = None
     dup_tol: float = 1e-8
-    retrack_rounds: int = 3
+    retrack_rounds: int = 2
+
+
+def conservative_opts() -> L.TrackOpts_:
+    """Re-tracking settings: float64, tight corrector, large divergence
+    radius, no end-zone shortcuts."""
+    return L.default_track_opts(L.NPHC_FP64).copy(corr_tol=1e-10, R_inf=1e8, grow_cap=0.0,
+                                                   hmin_rel=0.0)
 
 
 def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None, stream=None,
-        ids: Optional[torch.Tensor] = None) -> Buffers:
-    """Enqueue the whole pipeline on the stream (no host synchronisation)."""
+        events: Optional[Dict] = None) -> Buffers:
+    """Enqueue the whole pipeline on the stream (no host synchronisation).
+    events: optional dict of torch.cuda.Event recorded (same stream) around the
+    main tracking launch ("track_begin"/"track_end") and the float64
+    continuation ("resume_begin"/"resume_end"), and an optional callable
+    "after_track" invoked right after the main tracking launch is enqueued."""
     lib = L.lib()
     prec = PREC[opts.precision]
     b = bufs or allocate(batch, opts.precision)
@@ -168,16 +183,37 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     to = opts.track or L.default_track_opts(prec)
     co = opts.cert or L.default_cert_opts()
     clo = opts.classify or L.default_class_opts()
-    rt = opts.retrack or L.default_track_opts(L.NPHC_FP64)
+    rt = opts.retrack or conservative_opts()
     B = ctypes.byref(batch.c)
     cnt = b.counts
     c_sel = ctypes.c_void_p(cnt.data_ptr())              # counts[0]: list length
     c_dup = ctypes.c_void_p(cnt.data_ptr() + 8)          # counts[1]: marked duplicates
     stride = P
 
+    if events is not None:
+        events["track_begin"].record()
     L.check(lib.nphc_track_paths(B, None, P, None, prec, ctypes.byref(to), _p(b.z), stride,
-                                 _p(b.t), _p(b.status), _p(b.accepted), _p(b.rejected), _p(b.ws),
-                                 b.ws.numel(), s), "nphc_track_paths")
+                                 _p(b.t), _p(b.status), _p(b.accepted), _p(b.rejected),
+                                 _p(b.solves), _p(b.h), _p(b.ws), b.ws.numel(), s),
+            "nphc_track_paths")
+    if events is not None:
+        events["track_end"].record()
+        if "after_track" in events:
+            events["after_track"]()
+    if to.handoff_rejects > 0 or to.handoff_norm > 0 or to.handoff_steps > 0:
+        # float64 continuation of the paths the float32 tracker handed off
+        ro = opts.resume or L.default_track_opts(L.NPHC_FP64).copy(resume=1)
+        c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)   # counts[9]: handed off
+        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho, None, 0,
+                                s), "nphc_select")
+        if events is not None and "resume_begin" in events:
+            events["resume_begin"].record()
+        L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_ho, L.NPHC_FP64, ctypes.byref(ro),
+                                     _p(b.z), stride, _p(b.t), _p(b.status), _p(b.accepted),
+                                     _p(b.rejected), _p(b.solves), _p(b.h), _p(b.ws64),
+                                     b.ws64.numel(), s), "nphc_track_paths(resume)")
+        if events is not None and "resume_end" in events:
+            events["resume_end"].record()
     L.check(lib.nphc_refine_certify(B, None, P, None, ctypes.byref(co), _p(b.z), stride, _p(b.t),
                                     _p(b.status), _p(b.endpoint), _p(b.resid), _p(b.cond),
                                     _p(b.beta), _p(b.alpha), _p(b.alpha_real), s),
@@ -194,14 +230,13 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     hmax = rt.hmax
     for r in range(opts.retrack_rounds):
         hmax /= 4.0
-        o = L.TrackOpts_(min(rt.h0, hmax), hmax, rt.hmin, rt.corr_tol, rt.R_inf, rt.t_stall,
-                         rt.t_end, rt.max_corr, rt.max_steps, rt.predictor, 0)
+        o = rt.copy(h0=min(rt.h0, hmax), hmax=hmax)
         c_rt = ctypes.c_void_p(cnt.data_ptr() + 8 * (2 + r))  # counts[2+r]: re-tracked
         L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_FAIL, L.END_DUPLICATE), _p(b.ids),
                                 c_rt, None, 0, s), "nphc_select")
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_rt, L.NPHC_FP64, ctypes.byref(o), _p(b.z),
                                      stride, _p(b.t), _p(b.status), _p(b.accepted),
-                                     _p(b.rejected), _p(b.ws64), b.ws64.numel(), s),
+                                     _p(b.rejected), None, _p(b.h), _p(b.ws64), b.ws64.numel(), s),
                 "nphc_track_paths(retrack)")
         L.check(lib.nphc_refine_certify(B, _p(b.ids), P, c_rt, ctypes.byref(co), _p(b.z), stride,
                                         _p(b.t), _p(b.status), _p(b.endpoint), _p(b.resid),
@@ -235,7 +270,7 @@ class SystemResult:
         return np.bincount(self.index[~self.degenerate], minlength=self.N - 1)
 
 
-def collect(batch: Batch, b: Buffers, retrack_rounds: int = 3) -> Dict:
+def collect(batch: Batch, b: Buffers, retrack_rounds: int = 2) -> Dict:
     """Copy the compact results to the host and split them per system."""
     torch.cuda.synchronize()
     counts = b.counts.cpu().numpy()
@@ -272,8 +307,9 @@ def collect(batch: Batch, b: Buffers, retrack_rounds: int = 3) -> Dict:
                   ("diverged", L.END_DIVERGED), ("fail", L.END_FAIL), ("duplicate", L.END_DUPLICATE))}
     return dict(systems=systems, endpoint_counts=ep_counts,
                 retracked=[int(c) for c in counts[2:2 + retrack_rounds]],
+                handed_off=int(counts[9]),
                 duplicates_last=int(counts[1]), nonsingular=K,
-                status_counts=np.bincount(status, minlength=7).tolist())
+                status_counts=np.bincount(status, minlength=8).tolist())
 
 
 def find_all_sps(Js, gammas, precision: str = "fp32", opts: Optional[Options] = None, device="cuda"):
