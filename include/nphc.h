@@ -134,6 +134,12 @@ typedef struct nphc_track_opts {
     int32_t grid_blocks;     /* persistent grid size in 64-lane workgroups (0: one per resident wave slot) */
     int32_t handoff_steps;   /* > 0: stop with NPHC_PATH_HANDOFF after this many steps (bounds the
                                 float32 work of paths that creep through ill-conditioned stretches) */
+    double pred_tol;         /* > 0: reject a step whose first Newton correction exceeds
+                                pred_tol (1 + ||z||_inf) (the predictor was too far off: guards
+                                against jumping to a neighbouring path) */
+    int32_t step_ctrl;       /* 0: double h after three accepted steps, halve on rejection;
+                                1: scale h by (pred_tol / first correction)^(1/5) */
+    int32_t pad3;
 } nphc_track_opts;
 
 /* Endpoint refinement and certification settings. */
@@ -168,8 +174,9 @@ size_t nphc_track_workspace_size(const nphc_batch* b, int precision);
  * method": predictor-corrector continuation of every start solution).
  * Predictor: classical RK4 (or Euler) on the Davidenko equation
  * dz/dt = -H_z^{-1} H_t; corrector: up to max_corr Newton iterations at the
- * new t, each after the first at least halving the update; step size doubled
- * after three accepted steps in a row and halved on a rejected step.  One
+ * new t, each after the first at least halving the update, the first one
+ * bounded by pred_tol; step size doubled after three accepted steps in a row
+ * and halved on a rejected step.  One
  * persistent launch per call; each GPU lane tracks one path at a time and
  * takes the next queued item when its path ends.  precision NPHC_FP32 does
  * the predictor/corrector arithmetic in complex float32 (t and h stay

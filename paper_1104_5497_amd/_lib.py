@@ -50,7 +50,9 @@ class TrackOpts_(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("t_endzone", ctypes.c_double),
                 ("hmin_rel", ctypes.c_double), ("collapse_norm", ctypes.c_double),
                 ("grow_ratio", ctypes.c_double), ("grow_cap", ctypes.c_double),
-                ("grid_blocks", ctypes.c_int32), ("handoff_steps", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("handoff_steps", ctypes.c_int32),
+                ("pred_tol", ctypes.c_double), ("step_ctrl", ctypes.c_int32),
+                ("pad3", ctypes.c_int32)]
 
     def copy(self, **kw) -> "TrackOpts_":
         o = TrackOpts_()

@@ -1,0 +1,102 @@
+"""Launch and step-control tuning for a workload, cached as JSON.
+
+The tracker runs one path per lane (no lane-group variant: a path's reduced
+m x m system and its state live in one lane's registers, so splitting a path
+across lanes only adds cross-lane traffic).  What remains to tune per
+(device, ring sizes, precision) is
+  * the persistent grid (workgroups of 64 lanes; default: every resident
+    wave slot),
+  * the step-control schedule: the largest step h_max and, for float32, the
+    step budget after which a path is handed to the float64 continuation.
+Each candidate runs the whole pipeline; a candidate is only eligible when it
+reproduces the default run's certified real stationary points (counts and
+Hessian-index histograms per ring), and the fastest eligible one is kept.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import pipeline
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "nphc_autotune.json")
+
+
+def _key(batch: pipeline.Batch, precision: str) -> str:
+    arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
+    sizes = sorted(set(int(n) for n in batch.N_host))
+    return f"{arch}/N={','.join(map(str, sizes))}/systems={batch.num_systems}/{precision}"
+
+
+def _signature(res: Dict) -> List:
+    return [(s.theta.shape[0], s.histogram.tolist()) for s in res["systems"]]
+
+
+def _options(precision: str, params: Dict) -> pipeline.Options:
+    o = L.default_track_opts(pipeline.PREC[precision])
+    t = o.copy(**{k: v for k, v in params.items() if hasattr(o, k)})
+    opts = pipeline.Options(precision=precision, track=t)
+    if precision == "fp32":
+        opts.resume = L.default_track_opts(L.NPHC_FP64).copy(
+            resume=1, **{k: v for k, v in params.items() if k in ("grid_blocks",)})
+    return opts
+
+
+def _time(batch, opts, bufs, reps=2) -> float:
+    pipeline.run(batch, opts, bufs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pipeline.run(batch, opts, bufs)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def tune(batch: pipeline.Batch, precision: str = "fp32",
+         candidates: Optional[List[Dict]] = None, cache: Optional[str] = DEFAULT_CACHE,
+         reps: int = 2) -> Dict:
+    """Measure the candidates and return {"params", "ms", "default_ms"}."""
+    if candidates is None:
+        grids = [0, 2 * torch.cuda.get_device_properties(batch.device).multi_processor_count]
+        hmaxs = [0.05, 0.1]
+        steps = [120, 160, 240] if precision == "fp32" else [0]
+        candidates = [dict(grid_blocks=g, hmax=h, handoff_steps=s)
+                      for g, h, s in itertools.product(grids, hmaxs, steps)]
+    bufs = pipeline.allocate(batch, precision)
+    base_opts = pipeline.Options(precision=precision)
+    pipeline.run(batch, base_opts, bufs)
+    ref = _signature(pipeline.collect(batch, bufs))
+    base_ms = _time(batch, base_opts, bufs, reps)
+    best = dict(params={}, ms=base_ms)
+    for params in candidates:
+        opts = _options(precision, params)
+        ms = _time(batch, opts, bufs, reps)
+        if _signature(pipeline.collect(batch, bufs)) != ref:
+            continue
+        if ms < best["ms"]:
+            best = dict(params=params, ms=ms)
+    best["default_ms"] = base_ms
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        data = json.load(open(cache)) if os.path.exists(cache) else {}
+        data[_key(batch, precision)] = best
+        with open(cache, "w") as f:
+            json.dump(data, f, indent=1)
+    return best
+
+
+def load(batch: pipeline.Batch, precision: str = "fp32",
+         cache: Optional[str] = DEFAULT_CACHE) -> pipeline.Options:
+    """Options for this workload from the cache (defaults when absent)."""
+    if cache and os.path.exists(cache):
+        entry = json.load(open(cache)).get(_key(batch, precision))
+        if entry:
+            return _options(precision, entry["params"])
+    return pipeline.Options(precision=precision)

@@ -57,6 +57,9 @@ extern "C" void nphc_default_track_opts(int precision, nphc_track_opts* o)
     o->grow_cap = 0.5;
     o->grid_blocks = 0;
     o->handoff_steps = precision == NPHC_FP32 ? 160 : 0;
+    o->pred_tol = 1e-3;
+    o->step_ctrl = 0;
+    o->pad3 = 0;
 }
 
 extern "C" void nphc_default_cert_opts(nphc_cert_opts* o)

@@ -37,6 +37,9 @@ struct TrackOptsDev {
     double grow_cap;           // ... then the next step is at most grow_cap (1 - t)
     int32_t handoff_steps;     // > 0: stop with HANDOFF after this many steps
     int32_t pad2;
+    double pred_tol;           // > 0: reject when the first correction exceeds pred_tol (1 + ||z||)
+    int32_t step_ctrl;         // 0: double after three accepted steps; 1: predictor-error control
+    int32_t pad3;
 };
 
 struct TrackArgs {

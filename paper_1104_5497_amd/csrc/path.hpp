@@ -39,8 +39,8 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
 
     Point<T, M> zq = S.z;  // where the next linear solve is evaluated
     Point<T, M> w;         // RK4 accumulator, then the corrected point
-    bool ok = true, conv = false, bad = false;
-    T prev = T(0);
+    bool ok = true, conv = false, bad = false, too_far = false;
+    T prev = T(0), d1 = T(0), wn1 = T(1);
 
     for (int s = 0; s < nst + o.max_corr; ++s) {
         const bool pred = s < nst;
@@ -79,13 +79,23 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
             if (!sok) {
                 bad = true;
             } else {
+                const T nd = norm_inf<T, M>(d);
+                // path-jumping guard: the first correction measures the
+                // predictor's error; a large one means the step is too long
+                if (s == nst) {
+                    d1 = nd;
+                    wn1 = T(1) + norm_inf<T, M>(w);
+                    if (o.pred_tol > 0.0 && nd > T(o.pred_tol) * wn1) {
+                        bad = true;
+                        too_far = true;
+                    }
+                }
 #pragma unroll
                 for (int i = 0; i < M; ++i) {
                     w.x[i] = w.x[i] + d.x[i];
                     w.y[i] = w.y[i] + d.y[i];
                 }
                 zq = w;
-                const T nd = norm_inf<T, M>(d);
                 if (s > nst && nd > T(0.5) * prev) bad = true;
                 prev = nd;
                 if (!bad && nd <= T(o.corr_tol) * (T(1) + norm_inf<T, M>(w))) conv = true;
@@ -105,7 +115,12 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
         S.acc += 1;
         S.h_acc = hh;
         S.rej_run = 0;
-        if (++S.streak == 3) {
+        if (o.step_ctrl == 1 && o.pred_tol > 0.0) {
+            // predictor-error control: the RK4 local error scales as h^5
+            const double e = double(d1) / (o.pred_tol * double(wn1));
+            const double f = e > 1e-12 ? fmin(2.0, fmax(0.5, 0.8 * pow(e, -0.2))) : 2.0;
+            S.h = fmin(f * hh, o.hmax);
+        } else if (++S.streak == 3) {
             S.h = fmin(2.0 * hh, o.hmax);
             S.streak = 0;
         } else {
@@ -124,7 +139,12 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
         S.rej += 1;
         S.rej_run += 1;
         S.streak = 0;
-        S.h = 0.5 * hh;
+        if (too_far && o.step_ctrl == 1) {
+            const double e = double(d1) / (o.pred_tol * double(wn1));
+            S.h = hh * fmin(0.5, fmax(0.125, 0.8 * pow(e, -0.2)));
+        } else {
+            S.h = 0.5 * hh;
+        }
         // near t = 1 a step far below the remaining distance 1 - t means the
         // path is heading to infinity or to a singular endpoint
         const bool collapse = S.h < o.hmin ||

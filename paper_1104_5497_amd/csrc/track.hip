@@ -279,6 +279,8 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     A.o.grow_ratio = o->grow_ratio;
     A.o.grow_cap = o->grow_cap;
     A.o.handoff_steps = o->handoff_steps;
+    A.o.pred_tol = o->pred_tol;
+    A.o.step_ctrl = o->step_ctrl;
     A.out_stride = item_stride;
     A.z = z;
     A.t = t;

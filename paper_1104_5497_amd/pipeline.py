@@ -163,7 +163,7 @@ class Options:
 
 def conservative_opts() -> L.TrackOpts_:
     """Re-tracking settings: float64, tight corrector, large divergence
-    radius, no end-zone shortcuts."""
+    radius, no end-zone shortcuts (the predictor-error guard stays on)."""
     return L.default_track_opts(L.NPHC_FP64).copy(corr_tol=1e-10, R_inf=1e8, grow_cap=0.0,
                                                    hmin_rel=0.0)
 

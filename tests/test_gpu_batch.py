@@ -1,0 +1,86 @@
+"""Batched uneven sizes (384 disordered rings: 128 each of N = 5, 6, 7) in one
+persistent launch, the pipeline captured in a HIP graph, and the autotuner,
+against the oracle's stored per-ring results."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workload
+from tests._match import match_sets
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_batch.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("oracle_batch.json not generated")
+    with open(GOLDEN) as f:
+        return json.load(f)["rings"]
+
+
+def _check(res, rings):
+    assert len(res["systems"]) == len(rings)
+    for s, r in zip(res["systems"], rings):
+        nd = ~s.degenerate
+        assert s.N == r["N"]
+        assert int(nd.sum()) == r["num_real"], (r["ring"], int(nd.sum()), r["num_real"])
+        assert s.histogram.tolist() == r["histogram"], r["ring"]
+        if "theta" in r:
+            match_sets(s.theta[nd], s.index[nd], r["theta"], r["index"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch384_matches_oracle(precision):
+    from paper_1104_5497_amd import pipeline
+    rings = _golden()
+    B = workload.batch_rings(0)
+    print("batch384", precision, flush=True)
+    res = pipeline.find_all_sps(B.J, B.gamma, precision=precision)
+    assert res["batch"].num_items == 128 * (256 + 1024 + 4096)
+    _check(res, rings)
+
+
+def test_graph_replay_matches_eager():
+    """Capture the whole pipeline once; every replay (with eager work and
+    synchronisation in between) reproduces the eager result exactly."""
+    import torch
+    from paper_1104_5497_amd import graph, pipeline
+    rings = _golden()
+    B = workload.batch_rings(0)
+    sel = list(range(0, 384, 8))                 # 48 rings, sizes still mixed
+    batch = pipeline.Batch([B.J[i] for i in sel], [B.gamma[i] for i in sel])
+    opts = pipeline.Options(precision="fp32")
+    eager = pipeline.allocate(batch, "fp32")
+    pipeline.run(batch, opts, eager)
+    ref = pipeline.collect(batch, eager)
+    g = graph.PipelineGraph(batch, opts)
+    for rep in range(3):
+        g.bufs.endpoint.fill_(0)                 # eager work between replays
+        torch.cuda.synchronize()
+        b = g.replay()
+        torch.cuda.synchronize()
+        out = pipeline.collect(batch, b)
+        for s, r in zip(out["systems"], ref["systems"]):
+            assert np.array_equal(s.real_items, r.real_items)
+            assert np.array_equal(s.theta, r.theta)
+            assert np.array_equal(s.index, r.index)
+        assert torch.equal(b.z, eager.z)
+    _check(out, [rings[i] for i in sel])
+
+
+def test_autotune_keeps_results(tmp_path):
+    from paper_1104_5497_amd import autotune, pipeline
+    rings = _golden()
+    B = workload.batch_rings(0)
+    sel = list(range(0, 384, 16))
+    batch = pipeline.Batch([B.J[i] for i in sel], [B.gamma[i] for i in sel])
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(batch, "fp32", candidates=[dict(grid_blocks=512, handoff_steps=120),
+                                                    dict(hmax=0.1)], cache=cache, reps=1)
+    assert best["ms"] <= best["default_ms"]
+    opts = autotune.load(batch, "fp32", cache)
+    b = pipeline.run(batch, opts)
+    _check(pipeline.collect(batch, b), [rings[i] for i in sel])
