@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-ref", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path set would shard by path id across GPUs, "
@@ -145,6 +148,12 @@ def main():
     import workload
     from paper_1104_5497_amd import flops, pipeline
 
+    if a.copy_ref > 0:
+        src = torch.ones(a.copy_ref * 262144, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     J = workload.clean_ring_J(N_RING, SIGMA)
     gamma = workload.gamma_from_seed(GAMMA_SEED)
     m = N_RING - 1

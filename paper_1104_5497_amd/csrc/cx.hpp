@@ -8,6 +8,14 @@
 #define NPHC_HD __host__ __device__ __forceinline__
 #endif
 
+// Keeps the instruction scheduler from interleaving the phases on either side
+// (device code only), which bounds the number of values live at once.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NPHC_PHASE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define NPHC_PHASE() ((void)0)
+#endif
+
 namespace nphc {
 
 template <class T>

@@ -6,9 +6,41 @@
 
 namespace nphc {
 
+// The path's current point z and the RK4 accumulator w live outside the
+// register file: component i (0..2M-1, ordering x_0..x_{M-1}, y_0..y_{M-1})
+// of z is at base[i * stride], of w at base[(2M + i) * stride].  On the
+// device base points into LDS with stride 64 (one slot per lane, so a
+// wave's accesses to one component are consecutive); the register file is
+// left to the linear solve.
+template <class T, int M>
+struct PathStore {
+    cx<T>* base;
+    int stride;
+    NPHC_HD cx<T> z(int i) const { return base[i * stride]; }
+    NPHC_HD void set_z(int i, cx<T> v) const { base[i * stride] = v; }
+    NPHC_HD cx<T> w(int i) const { return base[(2 * M + i) * stride]; }
+    NPHC_HD void set_w(int i, cx<T> v) const { base[(2 * M + i) * stride] = v; }
+    NPHC_HD void load_z(Point<T, M>& p) const
+    {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            p.x[k] = z(k);
+            p.y[k] = z(M + k);
+        }
+    }
+    NPHC_HD void store_z(const Point<T, M>& p) const
+    {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            set_z(k, p.x[k]);
+            set_z(M + k, p.y[k]);
+        }
+    }
+};
+
 template <class T, int M>
 struct LanePath {
-    Point<T, M> z;
+    PathStore<T, M> st;
     double t, h;
     double h_acc;       // step size of the last accepted step
     double znorm;       // ||z|| after the last accepted step
@@ -29,16 +61,17 @@ NPHC_HD void start_point(int64_t pid, Point<T, M>& z)
 // method": predictor, then Newton's corrector; step control as documented in
 // nphc_track_paths).  Sets S.status when the path ends.
 template <class T, int M>
-NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
-                                          const TrackOptsDev& o, LanePath<T, M>& S)
+NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma, const TrackOptsDev& o,
+                       LanePath<T, M>& S)
 {
     const bool last = S.h >= o.t_end - S.t;
     const double hh = last ? (o.t_end - S.t) : S.h;
     const double t1 = last ? o.t_end : S.t + hh;
     const int nst = o.predictor == 0 ? 4 : 1;
+    const PathStore<T, M>& st = S.st;
 
-    Point<T, M> zq = S.z;  // where the next linear solve is evaluated
-    Point<T, M> w;         // RK4 accumulator, then the corrected point
+    Point<T, M> zq;        // where the next linear solve is evaluated; after the
+    st.load_z(zq);         // predictor, the point being corrected
     bool ok = true, conv = false, bad = false, too_far = false;
     T prev = T(0), d1 = T(0), wn1 = T(1);
 
@@ -53,27 +86,24 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
         S.solves += 1;
         if (pred) {
             ok = ok && sok;
-            const T ws = (s == 0 || s == 3) ? T(1) : T(2);
+            const T ws = (s == 0 || s == 3) ? T(1) : T(2);           // RK4 weights 1 2 2 1
+            const bool final_stage = (s == nst - 1);
+            const T f = T(nst == 4 ? hh / 6.0 : hh);
+            const T ch = T((s == 2 ? 1.0 : 0.5) * hh);               // next stage offset
 #pragma unroll
-            for (int i = 0; i < M; ++i) {
-                w.x[i] = (s == 0) ? d.x[i] : axpy(ws, d.x[i], w.x[i]);
-                w.y[i] = (s == 0) ? d.y[i] : axpy(ws, d.y[i], w.y[i]);
-            }
-            if (s < nst - 1) {
-                const T ch = T((s == 2 ? 1.0 : 0.5) * hh);  // next stage point
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    zq.x[i] = axpy(ch, d.x[i], S.z.x[i]);
-                    zq.y[i] = axpy(ch, d.y[i], S.z.y[i]);
+            for (int i = 0; i < 2 * M; ++i) {
+                const cx<T> di = i < M ? d.x[i] : d.y[i - M];
+                cx<T> wi = (s == 0) ? di : axpy(ws, di, st.w(i));
+                const cx<T> zi = st.z(i);
+                cx<T> next;
+                if (final_stage) {
+                    wi = axpy(f, wi, zi);                              // predicted point
+                    next = wi;
+                } else {
+                    st.set_w(i, wi);
+                    next = axpy(ch, di, zi);
                 }
-            } else {
-                const T f = T(nst == 4 ? hh / 6.0 : hh);
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    w.x[i] = axpy(f, w.x[i], S.z.x[i]);
-                    w.y[i] = axpy(f, w.y[i], S.z.y[i]);
-                }
-                zq = w;
+                if (i < M) zq.x[i] = next; else zq.y[i - M] = next;
             }
         } else {
             if (!sok) {
@@ -84,7 +114,7 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
                 // predictor's error; a large one means the step is too long
                 if (s == nst) {
                     d1 = nd;
-                    wn1 = T(1) + norm_inf<T, M>(w);
+                    wn1 = T(1) + norm_inf<T, M>(zq);
                     if (o.pred_tol > 0.0 && nd > T(o.pred_tol) * wn1) {
                         bad = true;
                         too_far = true;
@@ -92,25 +122,24 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
                 }
 #pragma unroll
                 for (int i = 0; i < M; ++i) {
-                    w.x[i] = w.x[i] + d.x[i];
-                    w.y[i] = w.y[i] + d.y[i];
+                    zq.x[i] = zq.x[i] + d.x[i];
+                    zq.y[i] = zq.y[i] + d.y[i];
                 }
-                zq = w;
                 if (s > nst && nd > T(0.5) * prev) bad = true;
                 prev = nd;
-                if (!bad && nd <= T(o.corr_tol) * (T(1) + norm_inf<T, M>(w))) conv = true;
+                if (!bad && nd <= T(o.corr_tol) * (T(1) + norm_inf<T, M>(zq))) conv = true;
             }
         }
     }
 
-    const T wn = norm_inf<T, M>(w);
+    const T wn = norm_inf<T, M>(zq);
     const bool finite = (wn - wn == T(0));
     if (ok && conv && !bad && !finite) {
         S.status = NPHC_PATH_FAIL_NONFINITE;
         return;
     }
     if (ok && conv && !bad) {
-        S.z = w;
+        st.store_z(zq);
         S.t = t1;
         S.acc += 1;
         S.h_acc = hh;
@@ -118,8 +147,8 @@ NPHC_HD void path_step(const Couplings<T, M>& C, cx<T> gamma,
         if (o.step_ctrl == 1 && o.pred_tol > 0.0) {
             // predictor-error control: the RK4 local error scales as h^5
             const double e = double(d1) / (o.pred_tol * double(wn1));
-            const double f = e > 1e-12 ? fmin(2.0, fmax(0.5, 0.8 * pow(e, -0.2))) : 2.0;
-            S.h = fmin(f * hh, o.hmax);
+            const double fct = e > 1e-12 ? fmin(2.0, fmax(0.5, 0.8 * pow(e, -0.2))) : 2.0;
+            S.h = fmin(fct * hh, o.hmax);
         } else if (++S.streak == 3) {
             S.h = fmin(2.0 * hh, o.hmax);
             S.streak = 0;

@@ -18,11 +18,10 @@ __device__ __forceinline__ void write_path(const TrackArgs& A, int64_t item, con
 {
     const int64_t st = A.out_stride;
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-        A.z[(2 * k) * st + item] = double(S.z.x[k].re);
-        A.z[(2 * k + 1) * st + item] = double(S.z.x[k].im);
-        A.z[(2 * (M + k)) * st + item] = double(S.z.y[k].re);
-        A.z[(2 * (M + k) + 1) * st + item] = double(S.z.y[k].im);
+    for (int i = 0; i < 2 * M; ++i) {
+        const cx<T> v = S.st.z(i);
+        A.z[(2 * i) * st + item] = double(v.re);
+        A.z[(2 * i + 1) * st + item] = double(v.im);
     }
     A.t[item] = S.t;
     A.status[item] = S.status;
@@ -37,10 +36,8 @@ __device__ __forceinline__ void read_path(const TrackArgs& A, int64_t item, Lane
 {
     const int64_t st = A.out_stride;
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-        S.z.x[k] = {T(A.z[(2 * k) * st + item]), T(A.z[(2 * k + 1) * st + item])};
-        S.z.y[k] = {T(A.z[(2 * (M + k)) * st + item]), T(A.z[(2 * (M + k) + 1) * st + item])};
-    }
+    for (int i = 0; i < 2 * M; ++i)
+        S.st.set_z(i, {T(A.z[(2 * i) * st + item]), T(A.z[(2 * i + 1) * st + item])});
     S.t = A.t[item];
     S.h = A.h[item];
     S.acc = A.accepted[item];
@@ -51,13 +48,15 @@ __device__ __forceinline__ void read_path(const TrackArgs& A, int64_t item, Lane
 // Process every queue position of class c.  UNIFORM: the batch has a single
 // system, whose couplings are then read through scalar loads.
 template <class T, int M, bool UNIFORM>
-__device__ void run_class(const TrackArgs& A, int c)
+__device__ void run_class(const TrackArgs& A, int c, cx<T>* lds)
 {
     const int lane = __lane_id();
     const int64_t qhi = A.q->qhi[c];
     const int64_t item_lo = A.cls[c].item_lo;
 
     LanePath<T, M> S;
+    S.st.base = lds + lane;
+    S.st.stride = 64;
     Couplings<T, M> C;
     cx<T> gamma;
     if (UNIFORM) {
@@ -94,13 +93,19 @@ __device__ void run_class(const TrackArgs& A, int c)
                         if (A.o.resume) {
                             read_path<T, M>(A, item, S);
                         } else {
-                            start_point<T, M>(pid, S.z);
+                            Point<T, M> z0;
+                            start_point<T, M>(pid, z0);
+                            S.st.store_z(z0);
                             S.t = 0.0;
                             S.h = A.o.h0;
                             S.acc = S.rej = S.solves = 0;
                         }
                         S.h_acc = S.h;
-                        S.znorm = double(norm_inf<T, M>(S.z));
+                        {
+                            Point<T, M> zc;
+                            S.st.load_z(zc);
+                            S.znorm = double(norm_inf<T, M>(zc));
+                        }
                         S.streak = S.rej_run = 0;
                         S.status = NPHC_PATH_PENDING;
                         active = true;
@@ -123,16 +128,19 @@ __device__ void run_class(const TrackArgs& A, int c)
 template <class T, int M>
 __global__ __launch_bounds__(64) void track_uniform_kernel(TrackArgs A)
 {
-    run_class<T, M, true>(A, 0);
+    // per-lane path state (point and RK4 accumulator): 4M complex per lane
+    __shared__ cx<T> lds[64 * 4 * M];
+    run_class<T, M, true>(A, 0, lds);
 }
 
 template <class T>
 __global__ __launch_bounds__(64) void track_batch_kernel(TrackArgs A)
 {
+    __shared__ cx<T> lds[64 * 4 * kBatchMaxM];
     for (int c = 0; c < A.num_classes; ++c) {
         switch (A.cls[c].M) {
 #define NPHC_CASE(m) \
-    case m: run_class<T, m, false>(A, c); break;
+    case m: run_class<T, m, false>(A, c, lds); break;
             NPHC_CASE(1) NPHC_CASE(2) NPHC_CASE(3) NPHC_CASE(4)
             NPHC_CASE(5) NPHC_CASE(6) NPHC_CASE(7) NPHC_CASE(8)
 #undef NPHC_CASE

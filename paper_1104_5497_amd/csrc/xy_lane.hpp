@@ -45,118 +45,106 @@ struct Point {
     cx<T> x[M], y[M];
 };
 
-// Sx, Sy and F at z.
-template <class T, int M>
-NPHC_HD void eval_sums(const Couplings<T, M>& C, const Point<T, M>& z,
-                                          cx<T> Sx[M], cx<T> Sy[M])
+// Constraint row k of the homotopy at (x_k, y_k): the coefficients a_k, b_k
+// and the minimum-norm particular solution (px_k, py_k) of
+// a_k dx_k + b_k dy_k = s_k, where s_k is the row's right-hand side
+// -(c1 (y_k^2 - 1) + c2 (x_k^2 + y_k^2 - 1)).
+template <class T>
+NPHC_HD void constraint_row(T t, cx<T> gt, cx<T> c1, T c2, cx<T> x, cx<T> y, cx<T>& a, cx<T>& b,
+                            cx<T>& px, cx<T>& py)
 {
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        cx<T> sx = {C.w(k), T(0)};
-        cx<T> sy = {T(0), T(0)};
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            if (j == k) continue;
-            T Jkj = C.J(k, j);
-            sx = sx + Jkj * z.x[j];
-            sy = sy + Jkj * z.y[j];
-        }
-        Sx[k] = sx;
-        Sy[k] = sy;
-    }
+    const cx<T> xx = x * x, yy = y * y;
+    const cx<T> ym1 = {yy.re - T(1), yy.im};
+    const cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
+    const cx<T> s = -(c1 * ym1 + c2 * con);
+    a = (T(2) * t) * x;
+    b = T(2) * (gt * y);
+    const cx<T> sk = s * rrcp(norm2(a) + norm2(b));
+    px = sk * conj(a);
+    py = sk * conj(b);
 }
-
 
 // Solves H_z(z, t) d = -H(z, t) (newton = true) or -H_t(z, t) (the Davidenko
 // tangent, newton = false).  gamma is the homotopy constant, t in [0, 1] and
 // omt = 1 - t (passed separately so that it keeps its relative precision near
 // t = 1).  Returns false when a pivot vanishes or the result is not finite.
+// Only R, its right-hand side and z stay live through the elimination; the
+// constraint parametrisation is recomputed for the back substitution.
 template <class T, int M>
-NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt,
-                                           bool newton, const Point<T, M>& z, Point<T, M>& d)
+NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool newton,
+                        const Point<T, M>& z, Point<T, M>& d)
 {
-    cx<T> Sx[M], Sy[M];
-    eval_sums<T, M>(C, z, Sx, Sy);
-
     const cx<T> g = omt * gamma;             // (1 - t) gamma
     const cx<T> gt = {g.re + t, g.im};       // g + t
     // -H = -(c1 Q + c2 F) with (c1, c2) = (g, t); -H_t = -(F - gamma Q), i.e.
     // (c1, c2) = (-gamma, 1)
     const cx<T> c1 = newton ? g : -gamma;
     const T c2 = newton ? t : T(1);
-    cx<T> r[M], s[M];                        // right-hand side (gradient rows, constraints)
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        cx<T> xk = z.x[k], yk = z.y[k];
-        cx<T> F = yk * Sx[k] - xk * Sy[k];
-        cx<T> xx = xk * xk, yy = yk * yk;
-        cx<T> xm1 = {xx.re - T(1), xx.im};
-        cx<T> ym1 = {yy.re - T(1), yy.im};
-        cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
-        r[k] = -(c1 * xm1 + c2 * F);
-        s[k] = -(c1 * ym1 + c2 * con);
-    }
 
-    // constraint-row parametrisation
-    cx<T> a[M], b[M], px[M], py[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        a[k] = (T(2) * t) * z.x[k];
-        b[k] = T(2) * (gt * z.y[k]);
-        T nrm = norm2(a[k]) + norm2(b[k]);
-        T inv = rrcp(nrm);
-        cx<T> sk = s[k] * inv;
-        px[k] = sk * conj(a[k]);
-        py[k] = sk * conj(b[k]);
-    }
-
-    // reduced matrix R (row-major, registers) and right-hand side
-    cx<T> R[M][M];
-    cx<T> v[M];
+    cx<T> R[M][M];   // reduced matrix (row-major, registers)
+    cx<T> v[M];      // its right-hand side, then the solution
     {
-        const cx<T> sg = csqrt(gt);
-        const T st = sqrt(t);
-        cx<T> Xs[M], Ys[M];
+        cx<T> px[M], py[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            Xs[k] = st * z.x[k];
-            Ys[k] = sg * z.y[k];
-        }
-        const T two_t = T(2) * t;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-#pragma unroll
-            for (int j = k + 1; j < M; ++j) {
-                cx<T> e = Ys[j] * Ys[k] + Xs[j] * Xs[k];
-                cx<T> val = (two_t * C.J(k, j)) * e;
-                R[k][j] = val;
-                R[j][k] = val;
-            }
+        for (int j = 0; j < M; ++j) {
+            cx<T> aj, bj;
+            constraint_row<T>(t, gt, c1, c2, z.x[j], z.y[j], aj, bj, px[j], py[j]);
         }
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            cx<T> Akk = (T(2) * g) * z.x[k] - t * Sy[k];
-            cx<T> Bkk = t * Sx[k];
-            R[k][k] = Akk * b[k] - Bkk * a[k];
-            // sum_{j != k} (A_kj px_j + B_kj py_j) = t (y_k U_k - x_k W_k)
+            const cx<T> xk = z.x[k], yk = z.y[k];
+            cx<T> sx = {C.w(k), T(0)}, sy = {T(0), T(0)};
             cx<T> U = {T(0), T(0)}, W = {T(0), T(0)};
 #pragma unroll
             for (int j = 0; j < M; ++j) {
                 if (j == k) continue;
-                T Jkj = C.J(k, j);
-                U = U + Jkj * px[j];
-                W = W + Jkj * py[j];
+                const T Jkj = C.J(k, j);
+                sx = axpy(Jkj, z.x[j], sx);
+                sy = axpy(Jkj, z.y[j], sy);
+                U = axpy(Jkj, px[j], U);
+                W = axpy(Jkj, py[j], W);
             }
-            cx<T> off = t * (z.y[k] * U - z.x[k] * W);
-            v[k] = r[k] - off - Akk * px[k] - Bkk * py[k];
+            const cx<T> F = yk * sx - xk * sy;
+            const cx<T> xx = xk * xk;
+            const cx<T> xm1 = {xx.re - T(1), xx.im};
+            const cx<T> rk = -(c1 * xm1 + c2 * F);
+            const cx<T> ak = (T(2) * t) * xk;
+            const cx<T> bk = T(2) * (gt * yk);
+            const cx<T> Akk = (T(2) * g) * xk - t * sy;
+            const cx<T> Bkk = t * sx;
+            R[k][k] = Akk * bk - Bkk * ak;
+            // sum_{j != k} (A_kj px_j + B_kj py_j) = t (y_k U - x_k W)
+            const cx<T> off = t * (yk * U - xk * W);
+            v[k] = rk - off - Akk * px[k] - Bkk * py[k];
+        }
+    }
+    // (px, py are dead from here on)
+    // off-diagonal entries 2 t J_kj ((g + t) y_j y_k + t x_j x_k)
+    {
+        const cx<T> sg = csqrt(gt);
+        const T st = sqrt(t);
+        const T two_t = T(2) * t;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const cx<T> Xk = st * z.x[k], Yk = sg * z.y[k];
+#pragma unroll
+            for (int j = k + 1; j < M; ++j) {
+                const cx<T> e = (sg * z.y[j]) * Yk + (st * z.x[j]) * Xk;
+                const cx<T> val = (two_t * C.J(k, j)) * e;
+                R[k][j] = val;
+                R[j][k] = val;
+            }
         }
     }
 
-    // Gaussian elimination with partial pivoting, right-hand side attached.
+
+    NPHC_PHASE();
+    // Gaussian elimination with partial pivoting, right-hand side attached;
+    // the reciprocal of pivot k replaces R[k][k].
     bool ok = true;
-    cx<T> dinv[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
+        NPHC_PHASE();
         T best = abs1(R[k][k]);
         int p = k;
 #pragma unroll
@@ -169,7 +157,7 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt,
         ok = ok && (best > T(0));
         if (k + 1 < M) {
             cx<T> rowk[M];
-            cx<T> vk = v[k];
+            const cx<T> vk = v[k];
 #pragma unroll
             for (int j = k; j < M; ++j) rowk[j] = R[k][j];
 #pragma unroll
@@ -177,39 +165,43 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt,
                 const bool sw = (p == i);
 #pragma unroll
                 for (int j = k; j < M; ++j) {
-                    cx<T> ri = R[i][j];
+                    const cx<T> ri = R[i][j];
                     R[k][j] = sel(sw, ri, R[k][j]);
                     R[i][j] = sel(sw, rowk[j], ri);
                 }
-                cx<T> vi = v[i];
+                const cx<T> vi = v[i];
                 v[k] = sel(sw, vi, v[k]);
                 v[i] = sel(sw, vk, vi);
             }
         }
-        cx<T> inv = rcp(R[k][k]);
-        dinv[k] = inv;
+        const cx<T> inv = rcp(R[k][k]);
+        R[k][k] = inv;
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
-            cx<T> l = R[i][k] * inv;
+            const cx<T> l = R[i][k] * inv;
 #pragma unroll
             for (int j = k + 1; j < M; ++j) R[i][j] = fnma(l, R[k][j], R[i][j]);
             v[i] = fnma(l, v[k], v[i]);
         }
     }
+    NPHC_PHASE();
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
         cx<T> acc = v[i];
 #pragma unroll
         for (int j = i + 1; j < M; ++j) acc = fnma(R[i][j], v[j], acc);
-        v[i] = acc * dinv[i];
+        v[i] = acc * R[i][i];
     }
 
-    // back to the full unknowns
+    NPHC_PHASE();
+    // back to the full unknowns: (dx_k, dy_k) = v_k (b_k, -a_k) + (px_k, py_k)
     T mag = T(0);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        d.x[k] = fma(b[k], v[k], px[k]);
-        d.y[k] = fnma(a[k], v[k], py[k]);
+        cx<T> ak, bk, pxk, pyk;
+        constraint_row<T>(t, gt, c1, c2, z.x[k], z.y[k], ak, bk, pxk, pyk);
+        d.x[k] = fma(bk, v[k], pxk);
+        d.y[k] = fnma(ak, v[k], pyk);
         mag = fmax(mag, fmax(absmax(d.x[k]), absmax(d.y[k])));
     }
     ok = ok && (mag - mag == T(0));  // false for inf and NaN
