@@ -83,7 +83,8 @@ def attribute_work(pipeline, batch, bufs, precision, m):
     # (re-tracked paths restart their step counters and pass no solve counter)
     s2 = int(bufs.solves.sum()) - s1
     st2 = max(0, int((bufs.accepted + bufs.rejected).sum()) - st1)
-    return dict(track=flops.kernel_flops(m, s1, st1), track_solves=s1,
+    return dict(track=flops.kernel_flops(m, s1, st1, wide_residual=(precision == "fp32")),
+                track_solves=s1,
                 resume=flops.kernel_flops(m, s2, st2), resume_solves=s2)
 
 

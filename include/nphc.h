@@ -179,8 +179,11 @@ size_t nphc_track_workspace_size(const nphc_batch* b, int precision);
  * and halved on a rejected step.  One
  * persistent launch per call; each GPU lane tracks one path at a time and
  * takes the next queued item when its path ends.  precision NPHC_FP32 does
- * the predictor/corrector arithmetic in complex float32 (t and h stay
- * float64).  With handoff_rejects > 0 a path whose step size collapses (or
+ * the linear algebra (Jacobian, tangent, elimination) in complex float32 but
+ * keeps the current point in float64 and evaluates the Newton right-hand side
+ * -H in float64 (mixed-precision Newton: the corrector converges to the
+ * float64 path, not to float32 rounding noise); t and h are float64.  With
+ * handoff_rejects > 0 a path whose step size collapses (or
  * that is rejected that many times in a row) stops with NPHC_PATH_HANDOFF and
  * its state is saved; a later call with resume = 1 continues it (normally in
  * float64).

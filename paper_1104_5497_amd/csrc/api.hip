@@ -51,12 +51,14 @@ extern "C" void nphc_default_track_opts(int precision, nphc_track_opts* o)
     o->handoff_rejects = precision == NPHC_FP32 ? 4 : 0;
     o->pad = 0;
     o->t_endzone = 0.9;
-    o->hmin_rel = 1e-3;
+    // float32: a step below 5% of 1 - t past the collapse norm means the
+    // float32 Jacobian has run out of precision; the path goes on in float64
+    o->hmin_rel = precision == NPHC_FP32 ? 0.05 : 1e-3;
     o->collapse_norm = 1e4;
     o->grow_ratio = 1.25;
     o->grow_cap = 0.5;
     o->grid_blocks = 0;
-    o->handoff_steps = precision == NPHC_FP32 ? 160 : 0;
+    o->handoff_steps = precision == NPHC_FP32 ? 240 : 0;
     o->pred_tol = 1e-3;
     o->step_ctrl = 0;
     o->pad3 = 0;

@@ -50,6 +50,7 @@ struct TrackArgs {
     const int64_t* path_off;   // device, num_systems + 1
     const double* gamma;       // device, 2 per system
     const void* Jpack;         // device, packed couplings in the tracking type
+    const void* Jpack64;       // device, the same in float64 (== Jpack for float64 tracking)
     const int64_t* Jpack_off;  // device, per system
     ClassDesc cls[kMaxClasses];
     // work list

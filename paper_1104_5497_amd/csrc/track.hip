@@ -13,15 +13,36 @@
 
 namespace nphc {
 
-template <class T, int M>
-__device__ __forceinline__ void write_path(const TrackArgs& A, int64_t item, const LanePath<T, M>& S)
+// float32 tracking runs on a float64 point with a float64 Newton residual;
+// float64 tracking keeps everything in float64.
+template <class T, int M> struct StoreFor { using type = PathStore<T, M>; };
+template <int M> struct StoreFor<float, M> { using type = MixedStore<M>; };
+
+// A lane's store inside the block's LDS (64 lanes x 64 M bytes).
+template <int M>
+__device__ __forceinline__ void make_store(cx<double>* lds, int lane, PathStore<double, M>& st)
+{
+    st.base = lds + lane;
+    st.stride = 64;
+}
+template <int M>
+__device__ __forceinline__ void make_store(cx<double>* lds, int lane, MixedStore<M>& st)
+{
+    st.zb = lds + lane;
+    st.wb = reinterpret_cast<cx<float>*>(lds + 64 * 2 * M) + lane;
+    st.db = st.wb + 64 * 2 * M;
+    st.stride = 64;
+}
+
+template <class Store, int M>
+__device__ __forceinline__ void write_path(const TrackArgs& A, int64_t item, const LanePath<Store, M>& S)
 {
     const int64_t st = A.out_stride;
 #pragma unroll
     for (int i = 0; i < 2 * M; ++i) {
-        const cx<T> v = S.st.z(i);
-        A.z[(2 * i) * st + item] = double(v.re);
-        A.z[(2 * i + 1) * st + item] = double(v.im);
+        const cx<double> v = S.st.get(i);
+        A.z[(2 * i) * st + item] = v.re;
+        A.z[(2 * i + 1) * st + item] = v.im;
     }
     A.t[item] = S.t;
     A.status[item] = S.status;
@@ -31,13 +52,13 @@ __device__ __forceinline__ void write_path(const TrackArgs& A, int64_t item, con
     if (A.h) A.h[item] = S.h;
 }
 
-template <class T, int M>
-__device__ __forceinline__ void read_path(const TrackArgs& A, int64_t item, LanePath<T, M>& S)
+template <class Store, int M>
+__device__ __forceinline__ void read_path(const TrackArgs& A, int64_t item, LanePath<Store, M>& S)
 {
     const int64_t st = A.out_stride;
 #pragma unroll
     for (int i = 0; i < 2 * M; ++i)
-        S.st.set_z(i, {T(A.z[(2 * i) * st + item]), T(A.z[(2 * i + 1) * st + item])});
+        S.st.put(i, {A.z[(2 * i) * st + item], A.z[(2 * i + 1) * st + item]});
     S.t = A.t[item];
     S.h = A.h[item];
     S.acc = A.accepted[item];
@@ -48,20 +69,21 @@ __device__ __forceinline__ void read_path(const TrackArgs& A, int64_t item, Lane
 // Process every queue position of class c.  UNIFORM: the batch has a single
 // system, whose couplings are then read through scalar loads.
 template <class T, int M, bool UNIFORM>
-__device__ void run_class(const TrackArgs& A, int c, cx<T>* lds)
+__device__ void run_class(const TrackArgs& A, int c, cx<double>* lds)
 {
+    using Store = typename StoreFor<T, M>::type;
     const int lane = __lane_id();
     const int64_t qhi = A.q->qhi[c];
-    const int64_t item_lo = A.cls[c].item_lo;
 
-    LanePath<T, M> S;
-    S.st.base = lds + lane;
-    S.st.stride = 64;
+    LanePath<Store, M> S;
+    make_store<M>(lds, lane, S.st);
     Couplings<T, M> C;
-    cx<T> gamma;
+    Couplings<double, M> C64;
+    cx<double> gamma64;
     if (UNIFORM) {
         C.p = reinterpret_cast<const T*>(A.Jpack);
-        gamma = {T(A.gamma[0]), T(A.gamma[1])};
+        C64.p = reinterpret_cast<const double*>(A.Jpack64);
+        gamma64 = {A.gamma[0], A.gamma[1]};
     }
     int64_t item = -1;
     bool active = false, drained = false;
@@ -88,14 +110,17 @@ __device__ void run_class(const TrackArgs& A, int c, cx<T>* lds)
                             const int64_t sys = find_system(A.path_off, A.num_systems, item);
                             pid = item - A.path_off[sys];
                             C.p = reinterpret_cast<const T*>(A.Jpack) + A.Jpack_off[sys];
-                            gamma = {T(A.gamma[2 * sys]), T(A.gamma[2 * sys + 1])};
+                            C64.p = reinterpret_cast<const double*>(A.Jpack64) + A.Jpack_off[sys];
+                            gamma64 = {A.gamma[2 * sys], A.gamma[2 * sys + 1]};
                         }
                         if (A.o.resume) {
-                            read_path<T, M>(A, item, S);
+                            read_path<Store, M>(A, item, S);
                         } else {
-                            Point<T, M> z0;
-                            start_point<T, M>(pid, z0);
-                            S.st.store_z(z0);
+#pragma unroll
+                            for (int k = 0; k < M; ++k) {
+                                S.st.put(k, {((pid >> k) & 1) ? -1.0 : 1.0, 0.0});
+                                S.st.put(M + k, {((pid >> (M + k)) & 1) ? -1.0 : 1.0, 0.0});
+                            }
                             S.t = 0.0;
                             S.h = A.o.h0;
                             S.acc = S.rej = S.solves = 0;
@@ -103,7 +128,7 @@ __device__ void run_class(const TrackArgs& A, int c, cx<T>* lds)
                         S.h_acc = S.h;
                         {
                             Point<T, M> zc;
-                            S.st.load_z(zc);
+                            S.st.load_point(zc);
                             S.znorm = double(norm_inf<T, M>(zc));
                         }
                         S.streak = S.rej_run = 0;
@@ -115,28 +140,30 @@ __device__ void run_class(const TrackArgs& A, int c, cx<T>* lds)
         }
         if (!__any(active)) break;
         if (active) {
-            path_step<T, M>(C, gamma, A.o, S);
+            const cx<T> gamma = {T(gamma64.re), T(gamma64.im)};
+            path_step<Store, M>(C, gamma, C64, gamma64, A.o, S);
             if (S.status != NPHC_PATH_PENDING) {
-                write_path<T, M>(A, item, S);
+                write_path<Store, M>(A, item, S);
                 active = false;
             }
         }
     }
-    (void)item_lo;
 }
 
+// Per-lane path state in LDS: 64 M bytes per lane (float64 tracking: point
+// and RK4 accumulator, 4M complex float64; float32 tracking: float64 point
+// plus float32 accumulator and increment).
 template <class T, int M>
 __global__ __launch_bounds__(64) void track_uniform_kernel(TrackArgs A)
 {
-    // per-lane path state (point and RK4 accumulator): 4M complex per lane
-    __shared__ cx<T> lds[64 * 4 * M];
+    __shared__ cx<double> lds[64 * 4 * M];
     run_class<T, M, true>(A, 0, lds);
 }
 
 template <class T>
 __global__ __launch_bounds__(64) void track_batch_kernel(TrackArgs A)
 {
-    __shared__ cx<T> lds[64 * 4 * kBatchMaxM];
+    __shared__ cx<double> lds[64 * 4 * kBatchMaxM];
     for (int c = 0; c < A.num_classes; ++c) {
         switch (A.cls[c].M) {
 #define NPHC_CASE(m) \
@@ -149,12 +176,13 @@ __global__ __launch_bounds__(64) void track_batch_kernel(TrackArgs A)
     }
 }
 
-// Setup: pack the couplings in the tracking type, and turn the classes' item
+// Setup: pack the couplings in the tracking type (and in float64 for the
+// wide residual of float32 tracking), and turn the classes' item
 // ranges into queue-position ranges (binary search in the sorted id list).
 template <class T>
 __global__ void track_setup_kernel(TrackArgs A, const double* J, const int64_t* J_off,
                                    int64_t count, const int64_t* count_dev, T* Jpack,
-                                   int64_t* Jpack_off)
+                                   double* Jpack64, int64_t* Jpack_off)
 {
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -181,6 +209,7 @@ __global__ void track_setup_kernel(TrackArgs A, const double* J, const int64_t* 
                 v = Jb[k * N + (N - 1)];
             }
             out[e] = T(v);
+            if (Jpack64 != static_cast<void*>(Jpack)) Jpack64[Jpack_off[b] + e] = v;
         }
     }
     if (blockIdx.x == 0 && tid < A.num_classes) {
@@ -216,7 +245,7 @@ namespace nphc {
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct TrackLayout {
-    size_t q_off, jp_off, jpo_off, total;
+    size_t q_off, jp_off, jp64_off, jpo_off, total;
 };
 
 static TrackLayout track_layout(const nphc_batch* b, int precision)
@@ -230,7 +259,9 @@ static TrackLayout track_layout(const nphc_batch* b, int precision)
     const size_t esz = precision == NPHC_FP32 ? sizeof(float) : sizeof(double);
     L.q_off = 0;
     L.jp_off = align256(sizeof(QueueState));
-    L.jpo_off = L.jp_off + align256(elems * esz);
+    // float32 tracking also needs the float64 pack (its Newton residual)
+    L.jp64_off = precision == NPHC_FP32 ? L.jp_off + align256(elems * esz) : L.jp_off;
+    L.jpo_off = L.jp64_off + align256(elems * sizeof(double));
     L.total = L.jpo_off + align256(sizeof(int64_t) * size_t(b->num_systems));
     return L;
 }
@@ -265,6 +296,7 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     A.path_off = b->path_off;
     A.gamma = b->gamma;
     A.Jpack = base + L.jp_off;
+    A.Jpack64 = base + L.jp64_off;
     A.Jpack_off = reinterpret_cast<const int64_t*>(base + L.jpo_off);
     A.ids = ids;
     A.q = reinterpret_cast<QueueState*>(base + L.q_off);
@@ -317,6 +349,7 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     if (setup_blocks < 1) setup_blocks = 1;
     hipLaunchKernelGGL(track_setup_kernel<T>, dim3(setup_blocks), dim3(256), 0, stream, A, b->J,
                        b->J_off, count, count_dev, reinterpret_cast<T*>(base + L.jp_off),
+                       reinterpret_cast<double*>(base + L.jp64_off),
                        reinterpret_cast<int64_t*>(base + L.jpo_off));
     if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
 

@@ -49,14 +49,20 @@ struct Point {
 // and the minimum-norm particular solution (px_k, py_k) of
 // a_k dx_k + b_k dy_k = s_k, where s_k is the row's right-hand side
 // -(c1 (y_k^2 - 1) + c2 (x_k^2 + y_k^2 - 1)).
-template <class T>
+// With EXT the right-hand side s_ext is given instead.
+template <class T, bool EXT = false>
 NPHC_HD void constraint_row(T t, cx<T> gt, cx<T> c1, T c2, cx<T> x, cx<T> y, cx<T>& a, cx<T>& b,
-                            cx<T>& px, cx<T>& py)
+                            cx<T>& px, cx<T>& py, cx<T> s_ext = cx<T>{})
 {
-    const cx<T> xx = x * x, yy = y * y;
-    const cx<T> ym1 = {yy.re - T(1), yy.im};
-    const cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
-    const cx<T> s = -(c1 * ym1 + c2 * con);
+    cx<T> s;
+    if constexpr (EXT) {
+        s = s_ext;
+    } else {
+        const cx<T> xx = x * x, yy = y * y;
+        const cx<T> ym1 = {yy.re - T(1), yy.im};
+        const cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
+        s = -(c1 * ym1 + c2 * con);
+    }
     a = (T(2) * t) * x;
     b = T(2) * (gt * y);
     const cx<T> sk = s * rrcp(norm2(a) + norm2(b));
@@ -64,15 +70,25 @@ NPHC_HD void constraint_row(T t, cx<T> gt, cx<T> c1, T c2, cx<T> x, cx<T> y, cx<
     py = sk * conj(b);
 }
 
+// Right-hand side computed inside the solve (from z, in the solve's type).
+struct OwnRhs {
+    static constexpr bool kExt = false;
+    template <class T> NPHC_HD cx<T> rg(int) const { return cx<T>{}; }
+    template <class T> NPHC_HD cx<T> rc(int) const { return cx<T>{}; }
+};
+
 // Solves H_z(z, t) d = -H(z, t) (newton = true) or -H_t(z, t) (the Davidenko
 // tangent, newton = false).  gamma is the homotopy constant, t in [0, 1] and
 // omt = 1 - t (passed separately so that it keeps its relative precision near
 // t = 1).  Returns false when a pivot vanishes or the result is not finite.
 // Only R, its right-hand side and z stay live through the elimination; the
 // constraint parametrisation is recomputed for the back substitution.
-template <class T, int M>
+// Rhs::kExt: the right-hand side is supplied by rhs (rg(k): gradient row k,
+// rc(k): constraint row k), e.g. -H evaluated in a wider type; H_z is still
+// formed from z in type T.
+template <class T, int M, class Rhs = OwnRhs>
 NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool newton,
-                        const Point<T, M>& z, Point<T, M>& d)
+                        const Point<T, M>& z, Point<T, M>& d, const Rhs& rhs = Rhs{})
 {
     const cx<T> g = omt * gamma;             // (1 - t) gamma
     const cx<T> gt = {g.re + t, g.im};       // g + t
@@ -88,7 +104,8 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool 
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             cx<T> aj, bj;
-            constraint_row<T>(t, gt, c1, c2, z.x[j], z.y[j], aj, bj, px[j], py[j]);
+            constraint_row<T, Rhs::kExt>(t, gt, c1, c2, z.x[j], z.y[j], aj, bj, px[j], py[j],
+                                         rhs.template rc<T>(j));
         }
 #pragma unroll
         for (int k = 0; k < M; ++k) {
@@ -107,7 +124,9 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool 
             const cx<T> F = yk * sx - xk * sy;
             const cx<T> xx = xk * xk;
             const cx<T> xm1 = {xx.re - T(1), xx.im};
-            const cx<T> rk = -(c1 * xm1 + c2 * F);
+            cx<T> rk;
+            if constexpr (Rhs::kExt) rk = rhs.template rg<T>(k);
+            else rk = -(c1 * xm1 + c2 * F);
             const cx<T> ak = (T(2) * t) * xk;
             const cx<T> bk = T(2) * (gt * yk);
             const cx<T> Akk = (T(2) * g) * xk - t * sy;
@@ -199,7 +218,8 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool 
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         cx<T> ak, bk, pxk, pyk;
-        constraint_row<T>(t, gt, c1, c2, z.x[k], z.y[k], ak, bk, pxk, pyk);
+        constraint_row<T, Rhs::kExt>(t, gt, c1, c2, z.x[k], z.y[k], ak, bk, pxk, pyk,
+                                     rhs.template rc<T>(k));
         d.x[k] = fma(bk, v[k], pxk);
         d.y[k] = fnma(ak, v[k], pyk);
         mag = fmax(mag, fmax(absmax(d.x[k]), absmax(d.y[k])));

@@ -18,6 +18,15 @@ vectors add 8 m per stage and 4 m per corrector update; the counter of linear
 solves the tracker reports covers predictor stages and corrector iterations
 alike, so the kernel's work is  solves * solve_flops(m) + steps * 48 m.
 
+float32 tracking evaluates each corrector right-hand side -H(z + dl) once
+more in float64 (nphc::MixedStore::wide_residual):
+  point z + dl                    4 m
+  sums Sx, Sy                     8 m (m - 1)
+  F, squares, the two rows        50 m
+  (1 - t) gamma                   4
+With four predictor solves per step, the corrector solves are
+solves - 4 * steps.
+
 For comparison, the dense formulation (Gaussian elimination on the full
 n x n Jacobian, n = 2m) costs dense_solve_flops(m) per solve.
 """
@@ -33,9 +42,17 @@ def step_overhead_flops(m: int) -> int:
     return 48 * m
 
 
-def kernel_flops(m: int, solves: int, steps: int) -> int:
-    """Total algorithmic flops of one tracking launch."""
-    return int(solves) * solve_flops(m) + int(steps) * step_overhead_flops(m)
+def wide_residual_flops(m: int) -> int:
+    return int(4 * m + 8 * m * (m - 1) + 50 * m + 4)
+
+
+def kernel_flops(m: int, solves: int, steps: int, wide_residual: bool = False) -> int:
+    """Total algorithmic flops of one tracking launch (wide_residual: float32
+    tracking, whose corrector right-hand sides are evaluated in float64)."""
+    f = int(solves) * solve_flops(m) + int(steps) * step_overhead_flops(m)
+    if wide_residual:
+        f += max(0, int(solves) - 4 * int(steps)) * wide_residual_flops(m)
+    return f
 
 
 def dense_solve_flops(m: int) -> int:

@@ -190,29 +190,30 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     c_dup = ctypes.c_void_p(cnt.data_ptr() + 8)          # counts[1]: marked duplicates
     stride = P
 
-    if events is not None:
+    events = events or {}
+    if "track_begin" in events:
         events["track_begin"].record()
     L.check(lib.nphc_track_paths(B, None, P, None, prec, ctypes.byref(to), _p(b.z), stride,
                                  _p(b.t), _p(b.status), _p(b.accepted), _p(b.rejected),
                                  _p(b.solves), _p(b.h), _p(b.ws), b.ws.numel(), s),
             "nphc_track_paths")
-    if events is not None:
+    if "track_end" in events:
         events["track_end"].record()
-        if "after_track" in events:
-            events["after_track"]()
+    if "after_track" in events:
+        events["after_track"]()
     if to.handoff_rejects > 0 or to.handoff_norm > 0 or to.handoff_steps > 0:
         # float64 continuation of the paths the float32 tracker handed off
         ro = opts.resume or L.default_track_opts(L.NPHC_FP64).copy(resume=1)
         c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)   # counts[9]: handed off
         L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho, None, 0,
                                 s), "nphc_select")
-        if events is not None and "resume_begin" in events:
+        if "resume_begin" in events:
             events["resume_begin"].record()
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_ho, L.NPHC_FP64, ctypes.byref(ro),
                                      _p(b.z), stride, _p(b.t), _p(b.status), _p(b.accepted),
                                      _p(b.rejected), _p(b.solves), _p(b.h), _p(b.ws64),
                                      b.ws64.numel(), s), "nphc_track_paths(resume)")
-        if events is not None and "resume_end" in events:
+        if "resume_end" in events:
             events["resume_end"].record()
     L.check(lib.nphc_refine_certify(B, None, P, None, ctypes.byref(co), _p(b.z), stride, _p(b.t),
                                     _p(b.status), _p(b.endpoint), _p(b.resid), _p(b.cond),
