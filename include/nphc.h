@@ -229,9 +229,15 @@ int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int64_t count,
  * does (one path per isolated nonsingular root).  Both are marked
  * NPHC_END_DUPLICATE.  *num_marked (device int64) receives the number of
  * items marked (it is overwritten, not accumulated).
+ * ids (device, sorted, *count_dev entries) lists the candidates, normally
+ * every NONSINGULAR item.  probe_ids == NULL: every pair of candidates is
+ * checked.  Otherwise only pairs with a probe (device, sorted,
+ * *probe_count_dev entries; e.g. the items just re-tracked) are checked:
+ * each probe that is NONSINGULAR against every other candidate of its system.
  */
 int nphc_mark_duplicates(const nphc_batch* b, const int64_t* ids, int64_t count,
-                         const int64_t* count_dev, double dup_tol, const double* z,
+                         const int64_t* count_dev, const int64_t* probe_ids,
+                         const int64_t* probe_count_dev, double dup_tol, const double* z,
                          int64_t item_stride, int32_t* endpoint, int64_t* num_marked,
                          void* workspace, size_t ws_bytes, hipStream_t stream);
 

@@ -100,7 +100,7 @@ def lib() -> ctypes.CDLL:
                                    vp, vp, vp, vp, vp, vp, sz, vp]
     L.nphc_refine_certify.argtypes = [pB, vp, i64, vp, ctypes.POINTER(CertOpts_), vp, i64, vp, vp,
                                       vp, vp, vp, vp, vp, vp, vp]
-    L.nphc_mark_duplicates.argtypes = [pB, vp, i64, vp, dbl, vp, i64, vp, vp, vp, sz, vp]
+    L.nphc_mark_duplicates.argtypes = [pB, vp, i64, vp, vp, vp, dbl, vp, i64, vp, vp, vp, sz, vp]
     L.nphc_select.argtypes = [vp, i64, u64, vp, vp, vp, sz, vp]
     L.nphc_select_workspace_size.argtypes = [i64]
     L.nphc_select_workspace_size.restype = sz

@@ -66,7 +66,7 @@ def tune(batch: pipeline.Batch, precision: str = "fp32",
     if candidates is None:
         grids = [0, 2 * torch.cuda.get_device_properties(batch.device).multi_processor_count]
         hmaxs = [0.05, 0.1]
-        steps = [120, 160, 240] if precision == "fp32" else [0]
+        steps = [120, 160, 200, 240] if precision == "fp32" else [0]
         candidates = [dict(grid_blocks=g, hmax=h, handoff_steps=s)
                       for g, h, s in itertools.product(grids, hmaxs, steps)]
     bufs = pipeline.allocate(batch, precision)

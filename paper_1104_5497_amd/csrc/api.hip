@@ -48,7 +48,7 @@ extern "C" void nphc_default_track_opts(int precision, nphc_track_opts* o)
     o->predictor = 0;
     o->resume = 0;
     o->handoff_norm = 0.0;
-    o->handoff_rejects = precision == NPHC_FP32 ? 4 : 0;
+    o->handoff_rejects = precision == NPHC_FP32 ? 8 : 0;
     o->pad = 0;
     o->t_endzone = 0.9;
     // float32: a step below 5% of 1 - t past the collapse norm means the
@@ -58,7 +58,7 @@ extern "C" void nphc_default_track_opts(int precision, nphc_track_opts* o)
     o->grow_ratio = 1.25;
     o->grow_cap = 0.5;
     o->grid_blocks = 0;
-    o->handoff_steps = precision == NPHC_FP32 ? 240 : 0;
+    o->handoff_steps = precision == NPHC_FP32 ? 200 : 0;
     o->pred_tol = 1e-3;
     o->step_ctrl = 0;
     o->pad3 = 0;

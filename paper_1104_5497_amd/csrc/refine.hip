@@ -1,13 +1,14 @@
 // refine.hip -- float64 endpoint refinement, certification and the
 // path-jump (duplicate endpoint) check.
 //
-// One wavefront per endpoint: lane i < 2m evaluates row i of F and F_z, and
-// the 2m x 2m system is solved by wave_gauss_jordan.
+// Refinement runs one endpoint per lane on the structured solver of the
+// tracker (nphc::solve_step at t = 1, where H = F): Newton on F, then the
+// certificate quantities, with ||F_z^{-1}||_F from the 2m columns of the
+// inverse (one solve per unit right-hand side).
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
-#include "wave_dense.hpp"
-#include "xy_dense.hpp"
+#include "xy_lane.hpp"
 
 namespace nphc {
 
@@ -31,53 +32,39 @@ struct RefineArgs {
     double *resid, *cond, *beta, *alpha, *alpha_real;
 };
 
+// Right-hand side chosen at run time: -F (j < 0, a Newton step) or e_j.
 template <int M>
-struct RefineShared {
-    GJShared<2 * M> gj;
-    cd z[2 * M];
-    double J[M * (M + 1) + 1];  // rows 0..M-1 of the ring's couplings, N = M+1 columns
+struct RefineRhs {
+    static constexpr bool kExt = true;
+    int j;
+    const Point<double, M>* F;
+    template <class T> NPHC_HD cx<T> rg(int k) const
+    {
+        return j < 0 ? -F->x[k] : cx<T>{k == j ? T(1) : T(0), T(0)};
+    }
+    template <class T> NPHC_HD cx<T> rc(int k) const
+    {
+        return j < 0 ? -F->y[k] : cx<T>{M + k == j ? T(1) : T(0), T(0)};
+    }
 };
 
-// Evaluates F and F_z at zs, then solves.  WITH_INV also returns the inverse
-// row and the Frobenius norms; x = F_z^{-1} F is returned in `sol`.
-template <int M, bool WITH_INV>
-__device__ __forceinline__ bool newton_solve(RefineShared<M>& sh, int lane, cd& sol, double* Fmax,
-                                             double* Anorm2, double* Ainvnorm2)
-{
-    constexpr int NN = 2 * M;
-    cd row[NN], inv[NN];
-    cd F;
-    const double* Jrow = sh.J + (lane < M ? lane : 0) * (M + 1);
-    xy_row<M>(lane, Jrow, sh.z, row, F);
-    if (Fmax) *Fmax = wave_max(lane < NN ? sqrt(norm2(F)) : 0.0);
-    if (Anorm2) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < NN; ++j) s += norm2(row[j]);
-        *Anorm2 = wave_sum(lane < NN ? s : 0.0);
-    }
-#pragma unroll
-    for (int j = 0; j < NN; ++j) inv[j] = {(j == lane) ? 1.0 : 0.0, 0.0};
-    sol = F;
-    const bool ok = wave_gauss_jordan<NN, WITH_INV>(row, sol, inv, sh.gj);
-    if (WITH_INV && Ainvnorm2) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < NN; ++j) s += norm2(inv[j]);
-        *Ainvnorm2 = wave_sum(lane < NN ? s : 0.0);
-    }
-    return ok;
-}
+// Per endpoint, one sequence of linear solves at t = 1 (one solve site, so
+// that the register frame of the float64 solve exists once):
+//   NEWTON     z <- z + d, d = -F_z^{-1} F, until the update stops
+//              decreasing or is below tol (1 + |z|), at most max_iter times;
+//   CERT       at the refined z: beta = ||F_z^{-1} F||_2 (j = -1), then the
+//              columns F_z^{-1} e_j (j = 0..2m-1) for ||F_z^{-1}||_F;
+//   CERT_REAL  the same at Re z, for a nonsingular endpoint with
+//              max |Im z_k| <= real_tol (certificate of a real root).
+enum { PH_NEWTON = 0, PH_CERT = 1, PH_CERT_REAL = 2, PH_DONE = 3 };
 
 template <int M>
 __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
 {
-    constexpr int NN = 2 * M;
-    __shared__ RefineShared<M> sh;
-    const int lane = threadIdx.x;
+    const cx<double> none = {0.0, 0.0};
     int64_t n = A.count;
     if (A.count_dev) n = min(n, *A.count_dev);
-    // queue positions of this class
+    // list positions of this class
     int64_t lo = 0, hi = n;
     if (A.ids) {
         int64_t a = 0, b = n;
@@ -90,96 +77,128 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
         lo = A.item_lo;
         hi = A.item_hi;
     }
-
-    for (int64_t pos = lo + blockIdx.x; pos < hi; pos += gridDim.x) {
+    const int64_t step = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t pos = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; pos < hi; pos += step) {
         const int64_t g = A.ids ? A.ids[pos] : pos;
         const int64_t sys = find_system(A.path_off, A.num_systems, g);
-        const int N = M + 1;
-        const double* Jb = A.J + A.J_off[sys];
-        for (int e = lane; e < M * N; e += 64) sh.J[e] = Jb[(e / N) * N + (e % N)];
-        // B = sqrt(||J~||_F^2 + 4m) / 2 over the free spins' block
-        double jf = 0.0;
-        for (int e = lane; e < M * M; e += 64) {
-            const int r = e / M, c = e % M;
-            const double v = (r == c) ? 0.0 : Jb[r * N + c];
-            jf += v * v;
+        Couplings<double, M> C;
+        C.p = A.J + A.J_off[sys];
+        Point<double, M> z;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            z.x[k] = {A.z[(2 * k) * A.stride + g], A.z[(2 * k + 1) * A.stride + g]};
+            z.y[k] = {A.z[(2 * (M + k)) * A.stride + g], A.z[(2 * (M + k) + 1) * A.stride + g]};
         }
-        const double Bnd = 0.5 * sqrt(wave_sum(jf) + 4.0 * M);
-        if (lane < NN) sh.z[lane] = {A.z[(2 * lane) * A.stride + g], A.z[(2 * lane + 1) * A.stride + g]};
-        __syncthreads();
         const int32_t st = A.status[g];
-        double zmod = wave_max(lane < NN ? sqrt(norm2(sh.z[lane])) : 0.0);
+        const double zmod0 = norm_mod<double, M>(z);
         const bool early = (st == NPHC_PATH_STALLED || st == NPHC_PATH_FAIL_MINSTEP ||
                             st == NPHC_PATH_FAIL_MAXSTEPS);
-        const bool big = !(zmod <= A.o.div_norm);
-        int32_t code;
+        const bool big = !(zmod0 <= A.o.div_norm);
+        int32_t code = NPHC_END_FAIL;
         double resid = INFINITY, cond = INFINITY, beta = INFINITY, alpha = INFINITY, areal = INFINITY;
         if (st == NPHC_PATH_DIVERGED || (early && big)) {
             code = NPHC_END_DIVERGED;
         } else if (st == NPHC_PATH_REACHED || st == NPHC_PATH_STALLED) {
-            // Newton on F at t = 1
-            double prev = INFINITY;
-            for (int it = 0; it < A.o.max_iter; ++it) {
-                cd d;
-                if (!newton_solve<M, false>(sh, lane, d, nullptr, nullptr, nullptr)) break;
-                const double nd = wave_max(lane < NN ? sqrt(norm2(d)) : 0.0);
-                if (!(nd == nd) || (it > 0 && nd > prev)) break;
-                if (lane < NN) sh.z[lane] = sh.z[lane] - d;
-                __syncthreads();
-                prev = nd;
-                const double zn = wave_max(lane < NN ? sqrt(norm2(sh.z[lane])) : 0.0);
-                if (nd <= A.o.tol * (1.0 + zn)) break;
-            }
-            zmod = wave_max(lane < NN ? sqrt(norm2(sh.z[lane])) : 0.0);
-            cd x;
-            double an2 = 0.0, ain2 = 0.0;
-            const bool ok = newton_solve<M, true>(sh, lane, x, &resid, &an2, &ain2);
-            if (ok) {
-                beta = sqrt(wave_sum(lane < NN ? norm2(x) : 0.0));
-                cond = sqrt(an2) * sqrt(ain2);
-                alpha = beta * sqrt(ain2) * Bnd;
-            }
-            const double scale = fmax(1.0, zmod * zmod);
+            // B = sqrt(||J~||_F^2 + 4m) / 2 over the free spins' block
+            double jf = 0.0;
+            for (int k = 0; k < M; ++k)
+                for (int j = 0; j < M; ++j)
+                    if (j != k) jf += C.J(k, j) * C.J(k, j);
+            const double Bnd = 0.5 * sqrt(jf + 4.0 * M);
             const bool reached_one = (st == NPHC_PATH_REACHED) && (A.t[g] == 1.0);
-            if (ok && reached_one && resid < A.o.res_tol * scale && cond < A.o.cond_max)
-                code = NPHC_END_NONSINGULAR;
-            else if (resid < A.o.sing_res * scale && !(cond < A.o.cond_max))
-                code = NPHC_END_SINGULAR;
-            else
-                code = NPHC_END_FAIL;
-            // certificate of the real projection
-            const double imax = wave_max(lane < NN ? fabs(sh.z[lane].im) : 0.0);
-            if (code == NPHC_END_NONSINGULAR && imax <= A.o.real_tol) {
-                __syncthreads();
-                cd keep = (lane < NN) ? sh.z[lane] : cd{0.0, 0.0};
-                if (lane < NN) sh.z[lane] = {keep.re, 0.0};
-                __syncthreads();
-                cd xr;
-                double ai2 = 0.0, rres = 0.0;
-                if (newton_solve<M, true>(sh, lane, xr, &rres, nullptr, &ai2)) {
-                    const double br = sqrt(wave_sum(lane < NN ? norm2(xr) : 0.0));
-                    areal = br * sqrt(ai2) * Bnd;
+
+            Point<double, M> F;       // F at the point of the current solves
+            eval_F<double, M>(C, z, F);
+            int phase = PH_NEWTON, it = 0, j = -1;
+            double prev = INFINITY, inv2 = 0.0, b2 = 0.0, an2 = 0.0, res = 0.0;
+            bool cok = true;
+            Point<double, M> zr;      // the real projection (CERT_REAL)
+            while (phase != PH_DONE) {
+                const Point<double, M>& zc = (phase == PH_CERT_REAL) ? zr : z;
+                Point<double, M> d;
+                const bool sok = solve_step<double, M>(C, none, 1.0, 0.0, true, zc, d, RefineRhs<M>{j, &F});
+                double dd = 0.0;
+#pragma unroll
+                for (int k = 0; k < M; ++k) dd += norm2(d.x[k]) + norm2(d.y[k]);
+                if (phase == PH_NEWTON) {
+                    const double nd = norm_mod<double, M>(d);
+                    bool stop = !sok || !(nd == nd) || (it > 0 && nd > prev);
+                    if (!stop) {
+#pragma unroll
+                        for (int k = 0; k < M; ++k) {
+                            z.x[k] = z.x[k] + d.x[k];
+                            z.y[k] = z.y[k] + d.y[k];
+                        }
+                        prev = nd;
+                        ++it;
+                        stop = (nd <= A.o.tol * (1.0 + norm_mod<double, M>(z))) || it >= A.o.max_iter;
+                    }
+                    eval_F<double, M>(C, z, F);   // residual at the (possibly) updated point
+                    if (stop) {
+                        res = norm_mod<double, M>(F);
+                        an2 = jac_frob2<double, M>(C, z);
+                        phase = PH_CERT;
+                        j = -1;
+                        cok = true;
+                        inv2 = 0.0;
+                    }
+                    continue;
                 }
-                __syncthreads();
-                if (lane < NN) sh.z[lane] = keep;
-                __syncthreads();
+                // certificate phases
+                cok = cok && sok;
+                if (j < 0) b2 = dd; else inv2 += dd;
+                if (++j < 2 * M) continue;
+                if (phase == PH_CERT) {
+                    resid = res;
+                    if (cok) {
+                        beta = sqrt(b2);
+                        cond = sqrt(an2) * sqrt(inv2);
+                        alpha = beta * sqrt(inv2) * Bnd;
+                    }
+                    const double zmod = norm_mod<double, M>(z);
+                    const double scale = fmax(1.0, zmod * zmod);
+                    if (cok && reached_one && resid < A.o.res_tol * scale && cond < A.o.cond_max)
+                        code = NPHC_END_NONSINGULAR;
+                    else if (resid < A.o.sing_res * scale && !(cond < A.o.cond_max))
+                        code = NPHC_END_SINGULAR;
+                    else
+                        code = NPHC_END_FAIL;
+                    double imax = 0.0;
+#pragma unroll
+                    for (int k = 0; k < M; ++k) imax = fmax(imax, fmax(fabs(z.x[k].im), fabs(z.y[k].im)));
+                    if (code == NPHC_END_NONSINGULAR && imax <= A.o.real_tol) {
+#pragma unroll
+                        for (int k = 0; k < M; ++k) {
+                            zr.x[k] = {z.x[k].re, 0.0};
+                            zr.y[k] = {z.y[k].re, 0.0};
+                        }
+                        eval_F<double, M>(C, zr, F);
+                        phase = PH_CERT_REAL;
+                        j = -1;
+                        cok = true;
+                        inv2 = 0.0;
+                    } else {
+                        phase = PH_DONE;
+                    }
+                } else {
+                    if (cok) areal = sqrt(b2) * sqrt(inv2) * Bnd;
+                    phase = PH_DONE;
+                }
             }
-            if (lane < NN) {
-                A.z[(2 * lane) * A.stride + g] = sh.z[lane].re;
-                A.z[(2 * lane + 1) * A.stride + g] = sh.z[lane].im;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                A.z[(2 * k) * A.stride + g] = z.x[k].re;
+                A.z[(2 * k + 1) * A.stride + g] = z.x[k].im;
+                A.z[(2 * (M + k)) * A.stride + g] = z.y[k].re;
+                A.z[(2 * (M + k) + 1) * A.stride + g] = z.y[k].im;
             }
-        } else {
-            code = NPHC_END_FAIL;
         }
-        if (lane == 0) {
-            A.endpoint[g] = code;
-            if (A.resid) A.resid[g] = resid;
-            if (A.cond) A.cond[g] = cond;
-            if (A.beta) A.beta[g] = beta;
-            if (A.alpha) A.alpha[g] = alpha;
-            if (A.alpha_real) A.alpha_real[g] = areal;
-        }
-        __syncthreads();
+        A.endpoint[g] = code;
+        if (A.resid) A.resid[g] = resid;
+        if (A.cond) A.cond[g] = cond;
+        if (A.beta) A.beta[g] = beta;
+        if (A.alpha) A.alpha[g] = alpha;
+        if (A.alpha_real) A.alpha_real[g] = areal;
     }
 }
 
@@ -199,6 +218,8 @@ struct DupArgs {
     int64_t stride;
     int32_t* endpoint;
     unsigned long long* marked;
+    const int64_t* probe;       // sorted items to check against all candidates (or null)
+    const int64_t* probe_count; // device
 };
 
 __global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
@@ -273,6 +294,43 @@ __global__ __launch_bounds__(256) void duplicates_kernel(DupArgs A)
     }
 }
 
+// Probe mode: one thread per probe item.  A probe that is a candidate
+// (NONSINGULAR) is compared with every other candidate of its system.
+__global__ __launch_bounds__(256) void duplicates_probe_kernel(DupArgs A)
+{
+    const int64_t K = *A.cand_count;
+    const int64_t R = *A.probe_count;
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < R;
+         r += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t gi = A.probe[r];
+        if (A.endpoint[gi] != NPHC_END_NONSINGULAR) continue;
+        const int64_t b = find_system(A.path_off, A.num_systems, gi);
+        const int64_t glo = A.path_off[b], ghi = A.path_off[b + 1];
+        int64_t a = 0, e = K;
+        while (a < e) { int64_t mid = (a + e) >> 1; if (A.cand[mid] < glo) a = mid + 1; else e = mid; }
+        const int64_t lo = a;
+        e = K;
+        while (a < e) { int64_t mid = (a + e) >> 1; if (A.cand[mid] < ghi) a = mid + 1; else e = mid; }
+        const int64_t hi = a;
+        const int n = 2 * (A.N[b] - 1);
+        const double re0 = A.z[gi], im0 = A.z[A.stride + gi];
+        for (int64_t j = lo; j < hi; ++j) {
+            const int64_t gj = A.cand[j];
+            if (gj == gi) continue;
+            if (fabs(A.z[gj] - re0) >= A.tol || fabs(A.z[A.stride + gj] - im0) >= A.tol) continue;
+            bool close = true;
+            for (int k = 1; k < n && close; ++k) {
+                close = fabs(A.z[(2 * k) * A.stride + gi] - A.z[(2 * k) * A.stride + gj]) < A.tol &&
+                        fabs(A.z[(2 * k + 1) * A.stride + gi] - A.z[(2 * k + 1) * A.stride + gj]) < A.tol;
+            }
+            if (close) {
+                mark_dup(A.endpoint, gi, A.marked);
+                mark_dup(A.endpoint, gj, A.marked);
+            }
+        }
+    }
+}
+
 int check_batch(const nphc_batch* b, bool* mixed, int* minN, int* maxN);
 
 }  // namespace nphc
@@ -323,9 +381,11 @@ extern "C" int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int6
         A.beta = beta;
         A.alpha = alpha;
         A.alpha_real = alpha_real;
+        // one endpoint per lane, several rounds per lane
         const int64_t items = A.item_hi - A.item_lo;
-        int64_t grid = int64_t(cus) * 16;
-        if (items < grid) grid = items;
+        int64_t grid = int64_t(cus) * 4;
+        const int64_t need = (items + 63) / 64;
+        if (need < grid) grid = need;
         if (grid < 1) grid = 1;
         const void* fn = nullptr;
         switch (A.M) {
@@ -344,7 +404,8 @@ extern "C" int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int6
 }
 
 extern "C" int nphc_mark_duplicates(const nphc_batch* b, const int64_t* ids, int64_t count,
-                                    const int64_t* count_dev, double dup_tol, const double* z,
+                                    const int64_t* count_dev, const int64_t* probe_ids,
+                                    const int64_t* probe_count_dev, double dup_tol, const double* z,
                                     int64_t item_stride, int32_t* endpoint, int64_t* num_marked,
                                     void* workspace, size_t ws_bytes, hipStream_t stream)
 {
@@ -353,6 +414,7 @@ extern "C" int nphc_mark_duplicates(const nphc_batch* b, const int64_t* ids, int
     int rc = check_batch(b, &mixed, &minN, &maxN);
     if (rc) return rc;
     if (!ids || !count_dev || !z || !endpoint || !num_marked || !(dup_tol > 0.0)) return NPHC_EINVAL;
+    if (probe_ids && !probe_count_dev) return NPHC_EINVAL;
     (void)count;
     (void)workspace;
     (void)ws_bytes;
@@ -376,10 +438,17 @@ extern "C" int nphc_mark_duplicates(const nphc_batch* b, const int64_t* ids, int
     A.stride = item_stride;
     A.endpoint = endpoint;
     A.marked = reinterpret_cast<unsigned long long*>(num_marked);
+    A.probe = probe_ids;
+    A.probe_count = probe_count_dev;
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, A.marked);
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NPHC_EHIP;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return NPHC_EHIP;
+    if (probe_ids) {
+        hipLaunchKernelGGL(duplicates_probe_kernel, dim3((unsigned)(cus * 4)), dim3(256), 0, stream, A);
+        if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
+        return NPHC_OK;
+    }
     const int64_t units = int64_t(b->num_systems) * A.tiles_per_system;
     int64_t grid = int64_t(cus) * 8;
     if (units < grid) grid = units;

@@ -199,15 +199,10 @@ __global__ void track_setup_kernel(TrackArgs A, const double* J, const int64_t* 
         const int m = N - 1;
         const double* Jb = J + J_off[b];
         T* out = Jpack + Jpack_off[b];
-        for (int e = tid; e < m * m + m; e += blockDim.x) {
-            double v;
-            if (e < m * m) {
-                const int k = e / m, j = e % m;
-                v = (k == j) ? 0.0 : Jb[k * N + j];
-            } else {
-                const int k = e - m * m;
-                v = Jb[k * N + (N - 1)];
-            }
+        // rows 0..m-1 of J (N columns each), diagonal zeroed
+        for (int e = tid; e < m * N; e += blockDim.x) {
+            const int k = e / N, j = e % N;
+            const double v = (k == j) ? 0.0 : Jb[e];
             out[e] = T(v);
             if (Jpack64 != static_cast<void*>(Jpack)) Jpack64[Jpack_off[b] + e] = v;
         }

@@ -31,13 +31,14 @@
 
 namespace nphc {
 
-// Couplings of one system, packed per ring: J[k*M + j] for free spins k, j
-// (zero diagonal) followed by w[k] = J_{k,N} (coupling to the fixed spin).
+// Couplings of one system: rows k = 0..M-1 of the N x N matrix (N = M + 1,
+// row-major), i.e. J_kj for free spins k, j at p[k*N + j] and the coupling to
+// the fixed spin w_k = J_{k,N} at p[k*N + M].  Diagonal entries are never read.
 template <class T, int M>
 struct Couplings {
     const T* p;
-    NPHC_HD T J(int k, int j) const { return p[k * M + j]; }
-    NPHC_HD T w(int k) const { return p[M * M + k]; }
+    NPHC_HD T J(int k, int j) const { return p[k * (M + 1) + j]; }
+    NPHC_HD T w(int k) const { return p[k * (M + 1) + M]; }
 };
 
 template <class T, int M>
@@ -75,6 +76,16 @@ struct OwnRhs {
     static constexpr bool kExt = false;
     template <class T> NPHC_HD cx<T> rg(int) const { return cx<T>{}; }
     template <class T> NPHC_HD cx<T> rc(int) const { return cx<T>{}; }
+};
+
+// Unit right-hand side e_j (j < M: gradient row j, j >= M: constraint row
+// j - M): the solve then returns column j of H_z^{-1}.
+template <int M>
+struct UnitRhs {
+    static constexpr bool kExt = true;
+    int j;
+    template <class T> NPHC_HD cx<T> rg(int k) const { return {k == j ? T(1) : T(0), T(0)}; }
+    template <class T> NPHC_HD cx<T> rc(int k) const { return {M + k == j ? T(1) : T(0), T(0)}; }
 };
 
 // Solves H_z(z, t) d = -H(z, t) (newton = true) or -H_t(z, t) (the Davidenko
@@ -226,6 +237,58 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool 
     }
     ok = ok && (mag - mag == T(0));  // false for inf and NaN
     return ok;
+}
+
+// The target system F(z) (t = 1): F.x[k] gradient row k, F.y[k] constraint row k.
+template <class T, int M>
+NPHC_HD void eval_F(const Couplings<T, M>& C, const Point<T, M>& z, Point<T, M>& F)
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        cx<T> sx = {C.w(k), T(0)}, sy = {T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j == k) continue;
+            sx = axpy(C.J(k, j), z.x[j], sx);
+            sy = axpy(C.J(k, j), z.y[j], sy);
+        }
+        F.x[k] = z.y[k] * sx - z.x[k] * sy;
+        const cx<T> xx = z.x[k] * z.x[k], yy = z.y[k] * z.y[k];
+        F.y[k] = {xx.re + yy.re - T(1), xx.im + yy.im};
+    }
+}
+
+// ||F_z(z)||_F^2.  Gradient row k: dF_k/dx_j = J_kj y_k, dF_k/dy_j = -J_kj x_k
+// (j != k), dF_k/dx_k = -Sy_k, dF_k/dy_k = Sx_k; constraint row k: 2 x_k, 2 y_k.
+template <class T, int M>
+NPHC_HD T jac_frob2(const Couplings<T, M>& C, const Point<T, M>& z)
+{
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        cx<T> sx = {C.w(k), T(0)}, sy = {T(0), T(0)};
+        T jj = T(0);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j == k) continue;
+            sx = axpy(C.J(k, j), z.x[j], sx);
+            sy = axpy(C.J(k, j), z.y[j], sy);
+            jj += C.J(k, j) * C.J(k, j);
+        }
+        const T xk = norm2(z.x[k]), yk = norm2(z.y[k]);
+        s += norm2(sx) + norm2(sy) + jj * (xk + yk) + T(4) * (xk + yk);
+    }
+    return s;
+}
+
+// max_k |z_k| (modulus)
+template <class T, int M>
+NPHC_HD T norm_mod(const Point<T, M>& z)
+{
+    T r = T(0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) r = fmax(r, fmax(norm2(z.x[k]), norm2(z.y[k])));
+    return sqrt(r);
 }
 
 // ||z||_inf in the max-of-|re|,|im| sense per coordinate (within sqrt(2) of

@@ -220,11 +220,12 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
                                     _p(b.beta), _p(b.alpha), _p(b.alpha_real), s),
             "nphc_refine_certify")
 
-    def dedupe():
+    def dedupe(probe=None, c_probe=None):
         L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_NONSINGULAR), _p(b.ids2), c_sel,
                                 None, 0, s), "nphc_select")
-        L.check(lib.nphc_mark_duplicates(B, _p(b.ids2), P, c_sel, opts.dup_tol, _p(b.z), stride,
-                                         _p(b.endpoint), c_dup, None, 0, s),
+        L.check(lib.nphc_mark_duplicates(B, _p(b.ids2), P, c_sel, _p(probe), c_probe,
+                                         opts.dup_tol, _p(b.z), stride, _p(b.endpoint), c_dup,
+                                         None, 0, s),
                 "nphc_mark_duplicates")
 
     dedupe()
@@ -243,7 +244,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
                                         _p(b.t), _p(b.status), _p(b.endpoint), _p(b.resid),
                                         _p(b.cond), _p(b.beta), _p(b.alpha), _p(b.alpha_real), s),
                 "nphc_refine_certify(retrack)")
-        dedupe()
+        # only the re-tracked endpoints can form new coincidences
+        dedupe(b.ids, c_rt)
     # classification of every nonsingular endpoint (the real filter is inside)
     c_cls = ctypes.c_void_p(cnt.data_ptr() + 8 * 8)       # counts[8]: nonsingular endpoints
     L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_NONSINGULAR), _p(b.ids2), c_cls, None,
