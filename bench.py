@@ -31,6 +31,16 @@ N_RING, SIGMA, GAMMA_SEED = 10, 1.0, 0
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X vector fp32 (AMD spec)
 FP64_VECTOR_PEAK = 78.6    # TFLOP/s, MI355X vector fp64 (AMD spec)
 
+# HBM traffic of one float32 tracking launch of this workload, from two
+# rocprofv3 counter runs of this script (FETCH_SIZE, then WRITE_SIZE, in KiB
+# per dispatch), each scaled by what the same counter reads for a plain
+# 256 MiB device copy in the same run (--copy-ref 256).  Valid only for the
+# tracker sources it was measured on: reported as null once they change.
+TRACKER_SOURCES = ("track.hip", "path.hpp", "xy_lane.hpp", "cx.hpp", "common.hpp")
+MEASURED_TRAFFIC = dict(
+    sources_sha256="6faa68e104bec31da2fb809e3a19fca8734936eb5675a17118f6954a64c43385",
+    fetch_kib=2638.5, fetch_scale=1.99975, write_kib=370360.875, write_scale=1.0)
+
 
 def fetch_real(b):
     """Compact results to the host: counts, then the classified candidates."""
@@ -110,6 +120,24 @@ def parity_vs_golden(out, m):
                 oracle_histogram=g["histogram"], sets_equal=ok, max_theta_err=err)
 
 
+def tracker_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACKER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1104_5497_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per float32 tracking launch, or None when not measured for the
+    current sources."""
+    t = MEASURED_TRAFFIC
+    if not t or t["sources_sha256"] != tracker_sources_sha():
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
+
 def cpu_baseline(J, gamma, sample, seed=1):
     """The oracle as it stands (track + refine) on a random sample of path ids."""
     import oracle
@@ -133,13 +161,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--print-sources-sha", action="store_true")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
+    if a.print_sources_sha:
+        print(tracker_sources_sha())
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path set would shard by path id across GPUs, "
               "but this build measures a single MI355X", file=sys.stderr)
@@ -182,18 +214,22 @@ def main():
                                     "FP32 track + FP64 continuation/endgame/re-track/certify/classify",
                            N=N_RING, sigma=SIGMA, gamma_seed=GAMMA_SEED, paths=P),
                roofline=dict(bound="alu", achieved=dom["achieved"], peak=dom["peak"],
-                             unit="TFLOP/s", frac=dom["frac"], traffic=None,
+                             unit="TFLOP/s", frac=dom["frac"],
+                             traffic=measured_traffic() if dom is k_track else None,
                              kernel=dom["kernel"], launch_ms=dom["launch_ms"],
                              flops_per_launch=dom["flops"], solve_flops=flops.solve_flops(m),
                              dense_equiv_flops=dom["solves"] * flops.dense_solve_flops(m)),
                kernels=[k_track, k_resume],
+               track_only_paths_per_s=P / ((k_track["launch_ms"] + k_resume["launch_ms"]) / 1e3),
                parity=parity)
     if not a.no_fp64:
         sec64, tr64, _, b64, out64 = time_pipeline(pipeline, batch, "fp64", a.steps, a.warmup)
         w64 = attribute_work(pipeline, batch, b64, "fp64", m)
         ach64 = w64["track"] / (np.mean(tr64) / 1e3) / 1e12
         res["fp64"] = dict(value=P / sec64, ms_per_step=sec64 * 1e3,
-                           track_ms=float(np.mean(tr64)), achieved_tflops=ach64,
+                           track_ms=float(np.mean(tr64)),
+                           track_only_paths_per_s=P / (np.mean(tr64) / 1e3),
+                           achieved_tflops=ach64,
                            frac_of_fp64_peak=ach64 / FP64_VECTOR_PEAK,
                            parity=parity_vs_golden(out64, m))
         res["speedup_vs_fp64"] = sec64 / sec32
