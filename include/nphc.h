@@ -230,16 +230,22 @@ int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int64_t count,
  * NPHC_END_DUPLICATE.  *num_marked (device int64) receives the number of
  * items marked (it is overwritten, not accumulated).
  * ids (device, sorted, *count_dev entries) lists the candidates, normally
- * every NONSINGULAR item.  probe_ids == NULL: every pair of candidates is
- * checked.  Otherwise only pairs with a probe (device, sorted,
- * *probe_count_dev entries; e.g. the items just re-tracked) are checked:
- * each probe that is NONSINGULAR against every other candidate of its system.
+ * every NONSINGULAR item; count is the capacity (an upper bound on
+ * *count_dev; candidates beyond it are ignored).  probe_ids == NULL: every
+ * pair of candidates is checked.  Otherwise only pairs with a probe (device,
+ * sorted, *probe_count_dev entries; e.g. the items just re-tracked) are
+ * checked: each probe that is NONSINGULAR against every other candidate of
+ * its system; with no probes the call does nothing on the device.
+ * The candidates are bucketed in a hash table (expected work linear in their
+ * number) held in the caller's workspace: nphc_duplicates_workspace_size(count)
+ * bytes, 256-byte aligned.  Batches need fewer than 2^20 systems.
  */
 int nphc_mark_duplicates(const nphc_batch* b, const int64_t* ids, int64_t count,
                          const int64_t* count_dev, const int64_t* probe_ids,
                          const int64_t* probe_count_dev, double dup_tol, const double* z,
                          int64_t item_stride, int32_t* endpoint, int64_t* num_marked,
                          void* workspace, size_t ws_bytes, hipStream_t stream);
+size_t nphc_duplicates_workspace_size(int64_t count);
 
 /*
  * Ordered compaction: writes, in increasing order, every item id g in

@@ -24,7 +24,8 @@ END_NONSINGULAR, END_SINGULAR, END_DIVERGED, END_FAIL, END_DUPLICATE = 10, 11, 1
 EXPORTS = [
     "nphc_default_track_opts", "nphc_default_cert_opts", "nphc_default_class_opts",
     "nphc_track_workspace_size", "nphc_track_paths", "nphc_refine_certify",
-    "nphc_mark_duplicates", "nphc_select", "nphc_select_workspace_size", "nphc_classify",
+    "nphc_mark_duplicates", "nphc_duplicates_workspace_size", "nphc_select",
+    "nphc_select_workspace_size", "nphc_classify",
     "nphc_adjoint", "nphc_strerror", "nphc_version",
 ]
 
@@ -101,6 +102,8 @@ def lib() -> ctypes.CDLL:
     L.nphc_refine_certify.argtypes = [pB, vp, i64, vp, ctypes.POINTER(CertOpts_), vp, i64, vp, vp,
                                       vp, vp, vp, vp, vp, vp, vp]
     L.nphc_mark_duplicates.argtypes = [pB, vp, i64, vp, vp, vp, dbl, vp, i64, vp, vp, vp, sz, vp]
+    L.nphc_duplicates_workspace_size.argtypes = [i64]
+    L.nphc_duplicates_workspace_size.restype = sz
     L.nphc_select.argtypes = [vp, i64, u64, vp, vp, vp, sz, vp]
     L.nphc_select_workspace_size.argtypes = [i64]
     L.nphc_select_workspace_size.restype = sz

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnphc.so")
-SOURCES = ["api.hip", "track.hip", "refine.hip", "select.hip", "classify.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "track.hip", "refine.hip", "duplicates.hip", "select.hip", "classify.hip",
+           "adjoint.hip"]
 HEADERS = ["cx.hpp", "xy_lane.hpp", "path.hpp", "xy_dense.hpp", "wave_dense.hpp", "common.hpp"]
 ARCH = os.environ.get("NPHC_OFFLOAD_ARCH", "gfx950")
 

@@ -1,5 +1,4 @@
-// refine.hip -- float64 endpoint refinement, certification and the
-// path-jump (duplicate endpoint) check.
+// refine.hip -- float64 endpoint refinement and certification.
 //
 // Refinement runs one endpoint per lane on the structured solver of the
 // tracker (nphc::solve_step at t = 1, where H = F): Newton on F, then the
@@ -202,135 +201,6 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
     }
 }
 
-// ---------------------------------------------------------------------------
-// duplicate endpoints
-// ---------------------------------------------------------------------------
-struct DupArgs {
-    int32_t num_systems;
-    int32_t n_max;             // unknowns of the largest ring
-    const int32_t* N;
-    const int64_t* path_off;
-    const int64_t* cand;       // sorted NONSINGULAR item ids (candidates)
-    const int64_t* cand_count; // device
-    int64_t tiles_per_system;
-    double tol;
-    const double* z;
-    int64_t stride;
-    int32_t* endpoint;
-    unsigned long long* marked;
-    const int64_t* probe;       // sorted items to check against all candidates (or null)
-    const int64_t* probe_count; // device
-};
-
-__global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
-
-__device__ __forceinline__ void mark_dup(int32_t* endpoint, int64_t g, unsigned long long* marked)
-{
-    const int old = atomicExch(&endpoint[g], NPHC_END_DUPLICATE);
-    if (old != NPHC_END_DUPLICATE) atomicAdd(marked, 1ull);
-}
-
-// Candidates of one system form a contiguous run of the sorted list.  Work
-// unit u = (system b, tile of 256 candidates); each thread owns one
-// candidate i of the tile and compares it with every later candidate j of the
-// same system, first on the first coordinate (staged through LDS), then on
-// all of them.
-__global__ __launch_bounds__(256) void duplicates_kernel(DupArgs A)
-{
-    __shared__ double s_re[256], s_im[256];
-    __shared__ int64_t s_g[256];
-    const int64_t K = *A.cand_count;
-    const int64_t units = int64_t(A.num_systems) * A.tiles_per_system;
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int64_t b = u / A.tiles_per_system;
-        const int64_t tile = u % A.tiles_per_system;
-        const int64_t glo = A.path_off[b], ghi = A.path_off[b + 1];
-        // candidate range of system b
-        int64_t lo = 0, hi = K;
-        {
-            int64_t a = 0, e = K;
-            while (a < e) { int64_t mid = (a + e) >> 1; if (A.cand[mid] < glo) a = mid + 1; else e = mid; }
-            lo = a;
-            e = K;
-            while (a < e) { int64_t mid = (a + e) >> 1; if (A.cand[mid] < ghi) a = mid + 1; else e = mid; }
-            hi = a;
-        }
-        const int64_t i0 = lo + tile * 256;
-        if (i0 >= hi) continue;  // uniform across the block
-        const int64_t i = i0 + threadIdx.x;
-        const bool have = i < hi;
-        const int64_t gi = have ? A.cand[i] : 0;
-        const int n = 2 * (A.N[b] - 1);
-        const double re0 = have ? A.z[gi] : 0.0;
-        const double im0 = have ? A.z[A.stride + gi] : 0.0;
-        for (int64_t j0 = i0; j0 < hi; j0 += 256) {
-            __syncthreads();
-            const int64_t jj = j0 + threadIdx.x;
-            if (jj < hi) {
-                const int64_t gj = A.cand[jj];
-                s_g[threadIdx.x] = gj;
-                s_re[threadIdx.x] = A.z[gj];
-                s_im[threadIdx.x] = A.z[A.stride + gj];
-            }
-            __syncthreads();
-            const int lim = (int)min<int64_t>(256, hi - j0);
-            if (have) {
-                for (int q = 0; q < lim; ++q) {
-                    if (j0 + q <= i) continue;
-                    if (fabs(s_re[q] - re0) >= A.tol || fabs(s_im[q] - im0) >= A.tol) continue;
-                    const int64_t gj = s_g[q];
-                    bool close = true;
-                    for (int k = 1; k < n && close; ++k) {
-                        close = fabs(A.z[(2 * k) * A.stride + gi] - A.z[(2 * k) * A.stride + gj]) < A.tol &&
-                                fabs(A.z[(2 * k + 1) * A.stride + gi] - A.z[(2 * k + 1) * A.stride + gj]) < A.tol;
-                    }
-                    if (close) {
-                        mark_dup(A.endpoint, gi, A.marked);
-                        mark_dup(A.endpoint, gj, A.marked);
-                    }
-                }
-            }
-        }
-    }
-}
-
-// Probe mode: one thread per probe item.  A probe that is a candidate
-// (NONSINGULAR) is compared with every other candidate of its system.
-__global__ __launch_bounds__(256) void duplicates_probe_kernel(DupArgs A)
-{
-    const int64_t K = *A.cand_count;
-    const int64_t R = *A.probe_count;
-    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < R;
-         r += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t gi = A.probe[r];
-        if (A.endpoint[gi] != NPHC_END_NONSINGULAR) continue;
-        const int64_t b = find_system(A.path_off, A.num_systems, gi);
-        const int64_t glo = A.path_off[b], ghi = A.path_off[b + 1];
-        int64_t a = 0, e = K;
-        while (a < e) { int64_t mid = (a + e) >> 1; if (A.cand[mid] < glo) a = mid + 1; else e = mid; }
-        const int64_t lo = a;
-        e = K;
-        while (a < e) { int64_t mid = (a + e) >> 1; if (A.cand[mid] < ghi) a = mid + 1; else e = mid; }
-        const int64_t hi = a;
-        const int n = 2 * (A.N[b] - 1);
-        const double re0 = A.z[gi], im0 = A.z[A.stride + gi];
-        for (int64_t j = lo; j < hi; ++j) {
-            const int64_t gj = A.cand[j];
-            if (gj == gi) continue;
-            if (fabs(A.z[gj] - re0) >= A.tol || fabs(A.z[A.stride + gj] - im0) >= A.tol) continue;
-            bool close = true;
-            for (int k = 1; k < n && close; ++k) {
-                close = fabs(A.z[(2 * k) * A.stride + gi] - A.z[(2 * k) * A.stride + gj]) < A.tol &&
-                        fabs(A.z[(2 * k + 1) * A.stride + gi] - A.z[(2 * k + 1) * A.stride + gj]) < A.tol;
-            }
-            if (close) {
-                mark_dup(A.endpoint, gi, A.marked);
-                mark_dup(A.endpoint, gj, A.marked);
-            }
-        }
-    }
-}
-
 int check_batch(const nphc_batch* b, bool* mixed, int* minN, int* maxN);
 
 }  // namespace nphc
@@ -399,60 +269,6 @@ extern "C" int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int6
         if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), args, 0, stream) != hipSuccess) return NPHC_EHIP;
         s = e;
     }
-    if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
-    return NPHC_OK;
-}
-
-extern "C" int nphc_mark_duplicates(const nphc_batch* b, const int64_t* ids, int64_t count,
-                                    const int64_t* count_dev, const int64_t* probe_ids,
-                                    const int64_t* probe_count_dev, double dup_tol, const double* z,
-                                    int64_t item_stride, int32_t* endpoint, int64_t* num_marked,
-                                    void* workspace, size_t ws_bytes, hipStream_t stream)
-{
-    bool mixed;
-    int minN, maxN;
-    int rc = check_batch(b, &mixed, &minN, &maxN);
-    if (rc) return rc;
-    if (!ids || !count_dev || !z || !endpoint || !num_marked || !(dup_tol > 0.0)) return NPHC_EINVAL;
-    if (probe_ids && !probe_count_dev) return NPHC_EINVAL;
-    (void)count;
-    (void)workspace;
-    (void)ws_bytes;
-    const int64_t total = b->path_off_host[b->num_systems];
-    if (item_stride < total) return NPHC_EINVAL;
-    DupArgs A = {};
-    A.num_systems = b->num_systems;
-    A.n_max = 2 * (maxN - 1);
-    A.N = b->N;
-    A.path_off = b->path_off;
-    A.cand = ids;
-    A.cand_count = count_dev;
-    int64_t maxp = 0;
-    for (int s = 0; s < b->num_systems; ++s) {
-        const int64_t p = b->path_off_host[s + 1] - b->path_off_host[s];
-        maxp = p > maxp ? p : maxp;
-    }
-    A.tiles_per_system = (maxp + 255) / 256;
-    A.tol = dup_tol;
-    A.z = z;
-    A.stride = item_stride;
-    A.endpoint = endpoint;
-    A.marked = reinterpret_cast<unsigned long long*>(num_marked);
-    A.probe = probe_ids;
-    A.probe_count = probe_count_dev;
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, A.marked);
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return NPHC_EHIP;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return NPHC_EHIP;
-    if (probe_ids) {
-        hipLaunchKernelGGL(duplicates_probe_kernel, dim3((unsigned)(cus * 4)), dim3(256), 0, stream, A);
-        if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
-        return NPHC_OK;
-    }
-    const int64_t units = int64_t(b->num_systems) * A.tiles_per_system;
-    int64_t grid = int64_t(cus) * 8;
-    if (units < grid) grid = units;
-    hipLaunchKernelGGL(duplicates_kernel, dim3((unsigned)grid), dim3(256), 0, stream, A);
     if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
     return NPHC_OK;
 }

@@ -110,6 +110,7 @@ class Buffers:
     counts: torch.Tensor       # small device counters (int64)
     ws: torch.Tensor           # tracker workspace (uint8)
     ws64: torch.Tensor         # tracker workspace for float64 re-tracking
+    wsdup: torch.Tensor        # duplicate-check hash table
     # classification outputs, per candidate position
     is_real: torch.Tensor
     theta: torch.Tensor
@@ -137,6 +138,8 @@ def allocate(batch: Batch, precision: str) -> Buffers:
         ids=torch.zeros(P, **i64), ids2=torch.zeros(P, **i64), counts=torch.zeros(16, **i64),
         ws=torch.zeros(max(int(ws_bytes), 256), dtype=torch.uint8, device=dev),
         ws64=torch.zeros(max(int(ws64_bytes), 256), dtype=torch.uint8, device=dev),
+        wsdup=torch.zeros(max(int(L.lib().nphc_duplicates_workspace_size(P)), 256),
+                          dtype=torch.uint8, device=dev),
         is_real=torch.zeros(P, **i32), theta=torch.zeros((m, P), **f64),
         energy=torch.zeros(P, **f64), index=torch.zeros(P, **i32),
         eig=torch.zeros((m, P), **f64), degenerate=torch.zeros(P, **i32))
@@ -225,7 +228,7 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
                                 None, 0, s), "nphc_select")
         L.check(lib.nphc_mark_duplicates(B, _p(b.ids2), P, c_sel, _p(probe), c_probe,
                                          opts.dup_tol, _p(b.z), stride, _p(b.endpoint), c_dup,
-                                         None, 0, s),
+                                         _p(b.wsdup), b.wsdup.numel(), s),
                 "nphc_mark_duplicates")
 
     dedupe()

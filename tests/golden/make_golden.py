@@ -3,7 +3,7 @@
 Calls only oracle/ (and the seeded input generators in workload/); nothing
 here comes from the HIP path.  Usage:
 
-    python tests/golden/make_golden.py ring10 ring8 batch adjoint9
+    python tests/golden/make_golden.py ring10 ring8 batch adjoint9 paper11
 
 Each file holds, per ring: N, sigma, gamma, the number of certified real
 nondegenerate stationary points, the Hessian-index histogram, and (unless the
@@ -50,6 +50,17 @@ def ring10():
     return dict(workload="clean XY ring N=10 sigma=1, gamma seed 0", rings=[rec])
 
 
+def paper11():
+    """The paper's N = 11 instance (alpha = 0.75, its normalisation K): the
+    paper reports 4774 stationary points."""
+    J = workload.paper_ring_J(11, 0.75)
+    g = workload.gamma_from_seed(0)
+    t0 = time.time()
+    res = oracle.find_all_sps(J, g)
+    rec = _ring_record(J, g, res, alpha=0.75, gamma_seed=0, seconds=time.time() - t0)
+    return dict(workload="paper ring N=11 alpha=0.75, gamma seed 0", rings=[rec])
+
+
 def ring8():
     rings = []
     for seed, sigma in enumerate((0.5, 1.0, 2.0)):
@@ -85,7 +96,7 @@ def adjoint9():
     return dict(workload="disordered ring N=9 sigma=1, J seed 0, gamma seed 0", rings=[rec])
 
 
-JOBS = {"ring10": ring10, "ring8": ring8, "batch": batch, "adjoint9": adjoint9}
+JOBS = {"ring10": ring10, "ring8": ring8, "batch": batch, "adjoint9": adjoint9, "paper11": paper11}
 
 if __name__ == "__main__":
     for name in sys.argv[1:] or list(JOBS):
