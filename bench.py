@@ -9,6 +9,10 @@ duplicated paths, real filter, Hessian-index classification, and the copy of
 the compact real stationary points to the host.  Inputs (couplings, gamma)
 are resident on the device before the timed region.
 
+--workload paper11 / paper13 time the paper's own alpha = 0.75 rings
+(1048576 and 16777216 paths) instead, checked against the stationary-point
+counts the paper reports.
+
 Prints one JSON line.  Extra keys: the all-float64 rate and the speed-up, the
 tracking kernel's roofline (algorithmic flops per launch over the launch's
 duration, timed with HIP events on the launch stream), parity of the real
@@ -27,7 +31,22 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "paths tracked/s at N=10 (262144 paths), FP32+FP64-endgame vs all-FP64"
-N_RING, SIGMA, GAMMA_SEED = 10, 1.0, 0
+GAMMA_SEED = 0
+# --workload: the default is the headline configuration; the paper's own
+# alpha = 0.75 rings (its reported stationary-point counts are the parity
+# check there) are extra measurements.
+WORKLOADS = {
+    "ring10": dict(N=10, kind="clean", p=1.0, metric=METRIC, golden="oracle_ring10.json",
+                   desc="clean XY ring N=10 sigma=1 h=0, 262144 total-degree paths"),
+    "paper11": dict(N=11, kind="paper", p=0.75, golden="oracle_paper11.json", paper_count=4774,
+                    metric="paths tracked/s on the paper's alpha=0.75 XY ring N=11 (1048576 paths), "
+                           "FP32+FP64-endgame vs all-FP64",
+                    desc="paper XY ring N=11 alpha=0.75 (paper's K), 1048576 total-degree paths"),
+    "paper13": dict(N=13, kind="paper", p=0.75, golden=None, paper_count=24830,
+                    metric="paths tracked/s on the paper's alpha=0.75 XY ring N=13 (16777216 paths), "
+                           "FP32+FP64-endgame vs all-FP64",
+                    desc="paper XY ring N=13 alpha=0.75 (paper's K), 16777216 total-degree paths"),
+}
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X vector fp32 (AMD spec)
 FP64_VECTOR_PEAK = 78.6    # TFLOP/s, MI355X vector fp64 (AMD spec)
 
@@ -98,26 +117,32 @@ def attribute_work(pipeline, batch, bufs, precision, m):
                 resume=flops.kernel_flops(m, s2, st2), resume_solves=s2)
 
 
-def parity_vs_golden(out, m):
+def parity_vs_golden(out, m, golden, paper_count=None):
     """Compare the certified real stationary points with the oracle's stored
-    result (same count, same Hessian indices, angles within 1e-10 mod 2 pi)."""
-    path = os.path.join(ROOT, "tests", "golden", "oracle_ring10.json")
-    if not os.path.exists(path):
-        return None
-    from tests._match import match_sets
-    g = json.load(open(path))["rings"][0]
+    result (same count, same Hessian indices, angles within 1e-10 mod 2 pi)
+    and, for the paper's rings, with the count the paper reports."""
     real = out["is_real"].numpy().astype(bool)
     deg = out["degenerate"].numpy().astype(bool)[real]
     th = out["theta"].numpy()[:m].T[real][~deg]
     idx = out["index"].numpy()[real][~deg]
     hist = np.bincount(idx, minlength=m).tolist()
-    try:
-        err = match_sets(th, idx, np.array(g["theta"]), np.array(g["index"]))
-        ok = True
-    except AssertionError:
-        err, ok = None, False
-    return dict(num_real=int(th.shape[0]), oracle_num_real=g["num_real"], histogram=hist,
-                oracle_histogram=g["histogram"], sets_equal=ok, max_theta_err=err)
+    res = dict(num_real=int(th.shape[0]), histogram=hist,
+               morse_sum=int(np.sum((-1) ** idx.astype(np.int64))))
+    if paper_count is not None:
+        res["paper_count"] = paper_count
+        res["matches_paper"] = int(th.shape[0]) == paper_count
+    path = os.path.join(ROOT, "tests", "golden", golden) if golden else None
+    if path and os.path.exists(path):
+        from tests._match import match_sets
+        g = json.load(open(path))["rings"][0]
+        try:
+            err = match_sets(th, idx, np.array(g["theta"]), np.array(g["index"]))
+            ok = True
+        except AssertionError:
+            err, ok = None, False
+        res.update(oracle_num_real=g["num_real"], oracle_histogram=g["histogram"], sets_equal=ok,
+                   max_theta_err=err)
+    return res
 
 
 def tracker_sources_sha():
@@ -138,12 +163,14 @@ def measured_traffic():
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
 
-def cpu_baseline(J, gamma, sample, seed=1):
+def cpu_baseline(J, gamma, sample, name, seed=1):
     """The oracle as it stands (track + refine) on a random sample of path ids."""
     import oracle
     threads = min(16, len(os.sched_getaffinity(0)))
     rng = np.random.default_rng(seed)
-    ids = np.sort(rng.choice(4 ** (N_RING - 1), size=sample, replace=False)).astype(np.int64)
+    P = 4 ** (J.shape[0] - 1)
+    sample = min(sample, P)
+    ids = np.sort(rng.choice(P, size=sample, replace=False)).astype(np.int64)
     s = oracle.System(J)
     t0 = time.perf_counter()
     r = s.track(gamma, ids, oracle.TrackOpts(), nthreads=threads)
@@ -151,7 +178,7 @@ def cpu_baseline(J, gamma, sample, seed=1):
     s.refine(r["z"][fin])
     dt = time.perf_counter() - t0
     return dict(value=sample / dt, unit="paths/s", cores=threads, kind="oracle",
-                sample=f"{sample} random path ids of the N=10 ring (seed {seed}), "
+                sample=f"{sample} random path ids of the {name} workload (seed {seed}), "
                        f"tracked and refined with the oracle's FP64 C tracker on {threads} threads; "
                        f"{dt:.1f} s")
 
@@ -159,6 +186,7 @@ def cpu_baseline(J, gamma, sample, seed=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ring10")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=65536)
@@ -187,35 +215,40 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    J = workload.clean_ring_J(N_RING, SIGMA)
+    W = WORKLOADS[a.workload]
+    N = W["N"]
+    J = (workload.clean_ring_J(N, W["p"]) if W["kind"] == "clean"
+         else workload.paper_ring_J(N, W["p"]))
     gamma = workload.gamma_from_seed(GAMMA_SEED)
-    m = N_RING - 1
+    m = N - 1
     P = 4 ** m
     batch = pipeline.Batch([J], [gamma], "cuda")
 
     sec32, tr32, rs32, b32, out32 = time_pipeline(pipeline, batch, "fp32", a.steps, a.warmup)
     w32 = attribute_work(pipeline, batch, b32, "fp32", m)
-    k_track = dict(kernel="nphc::track_uniform_kernel<float, 9>", dtype="f32",
+    k_track = dict(kernel=f"nphc::track_uniform_kernel<float, {m}>", dtype="f32",
                    launch_ms=float(np.mean(tr32)), flops=w32["track"], solves=w32["track_solves"],
                    peak=FP32_VECTOR_PEAK)
-    k_resume = dict(kernel="nphc::track_uniform_kernel<double, 9> (continuation)", dtype="f64",
+    k_resume = dict(kernel=f"nphc::track_uniform_kernel<double, {m}> (continuation)", dtype="f64",
                     launch_ms=float(np.mean(rs32)), flops=w32["resume"],
                     solves=w32["resume_solves"], peak=FP64_VECTOR_PEAK)
     for k in (k_track, k_resume):
         k["achieved"] = k["flops"] / (k["launch_ms"] / 1e3) / 1e12 if k["launch_ms"] > 0 else 0.0
         k["frac"] = k["achieved"] / k["peak"]
     dom = max((k_track, k_resume), key=lambda k: k["launch_ms"])
-    parity = parity_vs_golden(out32, m)
+    parity = parity_vs_golden(out32, m, W["golden"], W.get("paper_count"))
 
-    res = dict(metric=METRIC, value=P / sec32, unit="paths/s", n_gpus=1, steps=a.steps,
+    res = dict(metric=W["metric"], value=P / sec32, unit="paths/s", n_gpus=1, steps=a.steps,
                warmup=a.warmup, ms_per_step=sec32 * 1e3, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32+f64", data="synthetic",
-               config=dict(workload="clean XY ring N=10 sigma=1 h=0, 262144 total-degree paths, "
-                                    "FP32 track + FP64 continuation/endgame/re-track/certify/classify",
-                           N=N_RING, sigma=SIGMA, gamma_seed=GAMMA_SEED, paths=P),
+               config=dict(workload=W["desc"] + ", FP32 track + FP64 continuation/endgame/"
+                                                 "re-track/certify/classify",
+                           N=N, **({"sigma": W["p"]} if W["kind"] == "clean" else {"alpha": W["p"]}),
+                           gamma_seed=GAMMA_SEED, paths=P),
                roofline=dict(bound="alu", achieved=dom["achieved"], peak=dom["peak"],
                              unit="TFLOP/s", frac=dom["frac"],
-                             traffic=measured_traffic() if dom is k_track else None,
+                             traffic=(measured_traffic() if dom is k_track and a.workload == "ring10"
+                                      else None),
                              kernel=dom["kernel"], launch_ms=dom["launch_ms"],
                              flops_per_launch=dom["flops"], solve_flops=flops.solve_flops(m),
                              dense_equiv_flops=dom["solves"] * flops.dense_solve_flops(m)),
@@ -231,10 +264,10 @@ def main():
                            track_only_paths_per_s=P / (np.mean(tr64) / 1e3),
                            achieved_tflops=ach64,
                            frac_of_fp64_peak=ach64 / FP64_VECTOR_PEAK,
-                           parity=parity_vs_golden(out64, m))
+                           parity=parity_vs_golden(out64, m, W["golden"], W.get("paper_count")))
         res["speedup_vs_fp64"] = sec64 / sec32
     if not a.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(J, gamma, a.cpu_sample)
+        res["cpu_baseline"] = cpu_baseline(J, gamma, a.cpu_sample, a.workload)
     print(json.dumps(res), flush=True)
 
 
