@@ -59,22 +59,35 @@ def _sampled_paths(J, gamma, b, n, k, seed):
 
 
 def _check_counts(s, N):
+    from paper_1104_5497_amd import landscape
     nd = ~s.degenerate
     assert int(nd.sum()) == PAPER["counts"][str(N)]
     assert int(np.sum((-1) ** s.index[nd].astype(np.int64))) == 0
+    # the paper's landscape observations: global minimum theta = 0 (V = 0),
+    # smallest |det H|^(1/N) at a {0, pi} or twisted configuration
+    L = landscape.from_result(s)
+    assert L["global_min_kind"] == "zero_pi" and abs(L["global_min_V"]) < 1e-10
+    assert np.allclose(L["global_min_theta"], 0.0, atol=1e-9)
+    assert L["min_det_kind"] in ("zero_pi", "twisted"), L["min_det_theta"]
+    return L
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_paper_ring11(precision):
     print(f"paper ring N=11 {precision}", flush=True)
     J, gamma, s, b, n = _run(11, precision)
-    _check_counts(s, 11)
+    L = _check_counts(s, 11)
     _sampled_paths(J, gamma, b, n, 128, 5)
     if os.path.exists(GOLDEN11):
         g = json.load(open(GOLDEN11))["rings"][0]
         nd = ~s.degenerate
         assert s.histogram.tolist() == g["histogram"]
         match_sets(s.theta[nd], s.index[nd], np.array(g["theta"]), np.array(g["index"]))
+        # |det H|^(1/N) from the GPU's eigenvalues against numpy's determinant
+        # of the Hessian at the oracle's angles (as multisets)
+        dets = np.array([abs(np.linalg.det(oracle.hessian_theta(J, np.array(th))))
+                         for th in g["theta"]]) ** (1.0 / 11)
+        assert np.allclose(np.sort(L["det_root"]), np.sort(dets), rtol=1e-8)
 
 
 def test_paper_ring13():
