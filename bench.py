@@ -78,7 +78,7 @@ def time_pipeline(pipeline, batch, precision, steps, warmup):
         pipeline.run(batch, opts, bufs)
         fetch_real(bufs)
     torch.cuda.synchronize()
-    names = ("track_begin", "track_end", "resume_begin", "resume_end")
+    names = ("track_begin", "track_end", "resume_begin", "resume_end", "tail_begin", "tail_end")
     evs = [{k: torch.cuda.Event(enable_timing=True) for k in names} for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
@@ -86,35 +86,45 @@ def time_pipeline(pipeline, batch, precision, steps, warmup):
         out = fetch_real(bufs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    track_ms = [e["track_begin"].elapsed_time(e["track_end"]) for e in evs]
-    resume_ms = ([e["resume_begin"].elapsed_time(e["resume_end"]) for e in evs]
-                 if precision == "fp32" else [0.0])
-    return (t1 - t0) / steps, track_ms, resume_ms, bufs, out
+    def span(a, b):
+        out = []
+        for e in evs:
+            try:
+                out.append(e[a].elapsed_time(e[b]))
+            except ValueError:      # stage not run in this configuration
+                out.append(0.0)
+        return out
+    track_ms = span("track_begin", "track_end")
+    resume_ms = span("resume_begin", "resume_end") if precision == "fp32" else [0.0]
+    tail_ms = span("tail_begin", "tail_end")
+    return (t1 - t0) / steps, track_ms, resume_ms, tail_ms, bufs, out
 
 
 def attribute_work(pipeline, batch, bufs, precision, m):
     """Untimed run that splits the linear-solve count between the tracking
-    launch and the float64 continuation (the counter is cumulative per path)."""
+    launch, the per-lane float64 continuation and the lane-group tail (the
+    counters are cumulative per path: snapshots after each launch)."""
     import torch
     from paper_1104_5497_amd import flops
     snap = {}
 
-    def after_track():
-        snap["solves"] = bufs.solves.clone()
-        snap["steps"] = bufs.accepted + bufs.rejected
+    def snapshot(key):
+        def f():
+            snap[key] = (int(bufs.solves.sum()), int((bufs.accepted + bufs.rejected).sum()))
+        return f
 
     pipeline.run(batch, pipeline.Options(precision=precision), bufs,
-                 events={"track_begin": torch.cuda.Event(), "track_end": torch.cuda.Event(),
-                         "after_track": after_track})
+                 events={"after_track": snapshot("track"), "after_resume": snapshot("resume")})
     torch.cuda.synchronize()
-    s1, st1 = int(snap["solves"].sum()), int(snap["steps"].sum())
-    # the continuation's counts: final minus snapshot on the handed-off paths
-    # (re-tracked paths restart their step counters and pass no solve counter)
-    s2 = int(bufs.solves.sum()) - s1
-    st2 = max(0, int((bufs.accepted + bufs.rejected).sum()) - st1)
+    s1, st1 = snap["track"]
+    s2, st2 = snap["resume"][0] - s1, snap["resume"][1] - st1
+    # re-tracked paths restart their step counters and pass no solve counter
+    s3 = int(bufs.solves.sum()) - snap["resume"][0]
+    st3 = max(0, int((bufs.accepted + bufs.rejected).sum()) - snap["resume"][1])
     return dict(track=flops.kernel_flops(m, s1, st1, wide_residual=(precision == "fp32")),
                 track_solves=s1,
-                resume=flops.kernel_flops(m, s2, st2), resume_solves=s2)
+                resume=flops.kernel_flops(m, s2, st2), resume_solves=s2,
+                tail=flops.kernel_flops(m, s3, st3), tail_solves=s3)
 
 
 def parity_vs_golden(out, m, golden, paper_count=None):
@@ -224,7 +234,8 @@ def main():
     P = 4 ** m
     batch = pipeline.Batch([J], [gamma], "cuda")
 
-    sec32, tr32, rs32, b32, out32 = time_pipeline(pipeline, batch, "fp32", a.steps, a.warmup)
+    sec32, tr32, rs32, tl32, b32, out32 = time_pipeline(pipeline, batch, "fp32", a.steps,
+                                                        a.warmup)
     w32 = attribute_work(pipeline, batch, b32, "fp32", m)
     k_track = dict(kernel=f"nphc::track_uniform_kernel<float, {m}>", dtype="f32",
                    launch_ms=float(np.mean(tr32)), flops=w32["track"], solves=w32["track_solves"],
@@ -232,10 +243,13 @@ def main():
     k_resume = dict(kernel=f"nphc::track_uniform_kernel<double, {m}> (continuation)", dtype="f64",
                     launch_ms=float(np.mean(rs32)), flops=w32["resume"],
                     solves=w32["resume_solves"], peak=FP64_VECTOR_PEAK)
-    for k in (k_track, k_resume):
+    k_tail = dict(kernel=f"nphc::track_group_uniform_kernel<{m}> (lane-group tail)", dtype="f64",
+                  launch_ms=float(np.mean(tl32)), flops=w32["tail"], solves=w32["tail_solves"],
+                  peak=FP64_VECTOR_PEAK)
+    for k in (k_track, k_resume, k_tail):
         k["achieved"] = k["flops"] / (k["launch_ms"] / 1e3) / 1e12 if k["launch_ms"] > 0 else 0.0
         k["frac"] = k["achieved"] / k["peak"]
-    dom = max((k_track, k_resume), key=lambda k: k["launch_ms"])
+    dom = max((k_track, k_resume, k_tail), key=lambda k: k["launch_ms"])
     parity = parity_vs_golden(out32, m, W["golden"], W.get("paper_count"))
 
     res = dict(metric=W["metric"], value=P / sec32, unit="paths/s", n_gpus=1, steps=a.steps,
@@ -252,16 +266,18 @@ def main():
                              kernel=dom["kernel"], launch_ms=dom["launch_ms"],
                              flops_per_launch=dom["flops"], solve_flops=flops.solve_flops(m),
                              dense_equiv_flops=dom["solves"] * flops.dense_solve_flops(m)),
-               kernels=[k_track, k_resume],
-               track_only_paths_per_s=P / ((k_track["launch_ms"] + k_resume["launch_ms"]) / 1e3),
+               kernels=[k_track, k_resume, k_tail],
+               track_only_paths_per_s=P / ((k_track["launch_ms"] + k_resume["launch_ms"] +
+                                            k_tail["launch_ms"]) / 1e3),
                parity=parity)
     if not a.no_fp64:
-        sec64, tr64, _, b64, out64 = time_pipeline(pipeline, batch, "fp64", a.steps, a.warmup)
+        sec64, tr64, _, tl64, b64, out64 = time_pipeline(pipeline, batch, "fp64", a.steps,
+                                                         a.warmup)
         w64 = attribute_work(pipeline, batch, b64, "fp64", m)
         ach64 = w64["track"] / (np.mean(tr64) / 1e3) / 1e12
         res["fp64"] = dict(value=P / sec64, ms_per_step=sec64 * 1e3,
-                           track_ms=float(np.mean(tr64)),
-                           track_only_paths_per_s=P / (np.mean(tr64) / 1e3),
+                           track_ms=float(np.mean(tr64)), tail_ms=float(np.mean(tl64)),
+                           track_only_paths_per_s=P / ((np.mean(tr64) + np.mean(tl64)) / 1e3),
                            achieved_tflops=ach64,
                            frac_of_fp64_peak=ach64 / FP64_VECTOR_PEAK,
                            parity=parity_vs_golden(out64, m, W["golden"], W.get("paper_count")))

@@ -139,6 +139,12 @@ typedef struct nphc_track_opts {
                                 against jumping to a neighbouring path) */
     int32_t step_ctrl;       /* 0: double h after three accepted steps, halve on rejection;
                                 1: scale h by (pred_tol / first correction)^(1/5) */
+    int32_t lanes_per_path;  /* 1: one path per lane (throughput); 16: one path per group of 16
+                                lanes sharing each linear solve (lower latency per step, for the
+                                few long paths left at the end of a launch; float64 only) */
+    int32_t drain_steps;     /* > 0: once the launch's work queue is empty, a path still in flight
+                                stops with NPHC_PATH_HANDOFF after this many more steps (its state
+                                saved), so that the launch does not wait for its longest paths */
     int32_t pad3;
 } nphc_track_opts;
 

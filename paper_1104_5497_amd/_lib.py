@@ -53,6 +53,7 @@ class TrackOpts_(ctypes.Structure):
                 ("grow_ratio", ctypes.c_double), ("grow_cap", ctypes.c_double),
                 ("grid_blocks", ctypes.c_int32), ("handoff_steps", ctypes.c_int32),
                 ("pred_tol", ctypes.c_double), ("step_ctrl", ctypes.c_int32),
+                ("lanes_per_path", ctypes.c_int32), ("drain_steps", ctypes.c_int32),
                 ("pad3", ctypes.c_int32)]
 
     def copy(self, **kw) -> "TrackOpts_":

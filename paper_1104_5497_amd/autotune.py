@@ -40,12 +40,14 @@ def _signature(res: Dict) -> List:
 
 
 def _options(precision: str, params: Dict) -> pipeline.Options:
-    o = L.default_track_opts(pipeline.PREC[precision])
+    o = L.default_track_opts(pipeline.PREC[precision]).copy(
+        drain_steps=pipeline.DRAIN_DEFAULT[precision])
     t = o.copy(**{k: v for k, v in params.items() if hasattr(o, k)})
     opts = pipeline.Options(precision=precision, track=t)
     if precision == "fp32":
         opts.resume = L.default_track_opts(L.NPHC_FP64).copy(
-            resume=1, **{k: v for k, v in params.items() if k in ("grid_blocks",)})
+            resume=1, drain_steps=opts.cont_drain,
+            **{k: v for k, v in params.items() if k in ("grid_blocks",)})
     return opts
 
 

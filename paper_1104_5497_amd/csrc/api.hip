@@ -61,6 +61,8 @@ extern "C" void nphc_default_track_opts(int precision, nphc_track_opts* o)
     o->handoff_steps = precision == NPHC_FP32 ? 200 : 0;
     o->pred_tol = 1e-3;
     o->step_ctrl = 0;
+    o->lanes_per_path = 1;
+    o->drain_steps = 0;
     o->pad3 = 0;
 }
 

@@ -39,7 +39,7 @@ struct TrackOptsDev {
     int32_t pad2;
     double pred_tol;           // > 0: reject when the first correction exceeds pred_tol (1 + ||z||)
     int32_t step_ctrl;         // 0: double after three accepted steps; 1: predictor-error control
-    int32_t pad3;
+    int32_t drain_steps;       // > 0: steps a path may take after the queue drained, then HANDOFF
 };
 
 struct TrackArgs {

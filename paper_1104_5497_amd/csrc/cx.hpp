@@ -16,6 +16,16 @@
 #define NPHC_PHASE() ((void)0)
 #endif
 
+// Read-only data that no kernel writes while it is read (the couplings): the
+// constant address space lets wave-uniform reads use scalar loads into SGPRs
+// instead of vector loads into VGPRs.  Divergent addresses still work (they
+// become vector loads).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NPHC_RO __attribute__((address_space(4)))
+#else
+#define NPHC_RO
+#endif
+
 namespace nphc {
 
 template <class T>

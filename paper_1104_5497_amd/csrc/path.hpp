@@ -154,6 +154,19 @@ struct MixedStore {
     }
 };
 
+// The linear solve of one lane's own path.
+struct LaneSolver {
+    template <class T, int M>
+    NPHC_HD bool operator()(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool newton,
+                            const Point<T, M>& z, Point<T, M>& d) const
+    {
+        return solve_step<T, M>(C, gamma, t, omt, newton, z, d);
+    }
+};
+
+template <class S> constexpr bool kLaneSolver = false;
+template <> constexpr bool kLaneSolver<LaneSolver> = true;
+
 template <class Store, int M>
 struct LanePath {
     Store st;
@@ -177,10 +190,13 @@ NPHC_HD void start_point(int64_t pid, Point<T, M>& z)
 // method": predictor, then Newton's corrector; step control as documented in
 // nphc_track_paths).  Sets S.status when the path ends.  C and gamma are in the
 // solve's type; C64 and gamma64 (float64) serve a store with a wide residual.
-template <class Store, int M>
+// solver performs the linear solves (one lane, or a lane group whose lanes all
+// run this step on the same replicated state).
+template <class Store, int M, class Solver = LaneSolver>
 NPHC_HD void path_step(const Couplings<typename Store::Solve, M>& C,
                        cx<typename Store::Solve> gamma, const Couplings<double, M>& C64,
-                       cx<double> gamma64, const TrackOptsDev& o, LanePath<Store, M>& S)
+                       cx<double> gamma64, const TrackOptsDev& o, LanePath<Store, M>& S,
+                       const Solver& solver = Solver{})
 {
     using T = typename Store::Solve;
     const bool last = S.h >= o.t_end - S.t;
@@ -209,8 +225,11 @@ NPHC_HD void path_step(const Couplings<typename Store::Solve, M>& C,
             } else {
                 sok = solve_step<T, M>(C, gamma, T(tq), T(1.0 - tq), false, zq, d);
             }
-        } else {
+        } else if constexpr (kLaneSolver<Solver>) {
+            // (direct call: going through the policy object costs registers)
             sok = solve_step<T, M>(C, gamma, T(tq), T(1.0 - tq), !pred, zq, d);
+        } else {
+            sok = solver(C, gamma, T(tq), T(1.0 - tq), !pred, zq, d);
         }
         S.solves += 1;
         if (pred) {

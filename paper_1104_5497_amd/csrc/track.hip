@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "path.hpp"
+#include "xy_group.hpp"
 
 namespace nphc {
 
@@ -81,12 +82,13 @@ __device__ void run_class(const TrackArgs& A, int c, cx<double>* lds)
     Couplings<double, M> C64;
     cx<double> gamma64;
     if (UNIFORM) {
-        C.p = reinterpret_cast<const T*>(A.Jpack);
-        C64.p = reinterpret_cast<const double*>(A.Jpack64);
+        C.p = (const NPHC_RO T*)(A.Jpack);
+        C64.p = (const NPHC_RO double*)(A.Jpack64);
         gamma64 = {A.gamma[0], A.gamma[1]};
     }
     int64_t item = -1;
     bool active = false, drained = false;
+    int post = 0;  // steps of the current path since this wave saw the queue drained
 
     for (;;) {
         if (!drained) {
@@ -109,8 +111,8 @@ __device__ void run_class(const TrackArgs& A, int c, cx<double>* lds)
                         } else {
                             const int64_t sys = find_system(A.path_off, A.num_systems, item);
                             pid = item - A.path_off[sys];
-                            C.p = reinterpret_cast<const T*>(A.Jpack) + A.Jpack_off[sys];
-                            C64.p = reinterpret_cast<const double*>(A.Jpack64) + A.Jpack_off[sys];
+                            C.p = (const NPHC_RO T*)(A.Jpack) + A.Jpack_off[sys];
+                            C64.p = (const NPHC_RO double*)(A.Jpack64) + A.Jpack_off[sys];
                             gamma64 = {A.gamma[2 * sys], A.gamma[2 * sys + 1]};
                         }
                         if (A.o.resume) {
@@ -142,10 +144,129 @@ __device__ void run_class(const TrackArgs& A, int c, cx<double>* lds)
         if (active) {
             const cx<T> gamma = {T(gamma64.re), T(gamma64.im)};
             path_step<Store, M>(C, gamma, C64, gamma64, A.o, S);
+            if (drained) ++post;
+            if (S.status == NPHC_PATH_PENDING && A.o.drain_steps > 0 && post >= A.o.drain_steps)
+                S.status = NPHC_PATH_HANDOFF;
             if (S.status != NPHC_PATH_PENDING) {
                 write_path<Store, M>(A, item, S);
                 active = false;
             }
+        }
+    }
+}
+
+// One path per group of 16 lanes, float64 (4 paths per wave).  Every lane of
+// a group holds the path's scalars and point and runs the same step; the
+// linear solves are shared (xy_group.hpp); the group's point and RK4
+// accumulator sit in one LDS slot that all its lanes address.
+template <int M, bool UNIFORM>
+__device__ void run_class_group(const TrackArgs& A, int c, cx<double>* lds)
+{
+    using Store = PathStore<double, M>;
+    const int lane = __lane_id();
+    const int r = lane & (kGroup - 1);
+    const int grp = lane / kGroup;
+    const int64_t qhi = A.q->qhi[c];
+
+    LanePath<Store, M> S;
+    S.st.base = lds + grp;
+    S.st.stride = 64 / kGroup;
+    Couplings<double, M> C;
+    GroupRow<double, M> G;
+    cx<double> gamma;
+    if (UNIFORM) {
+        C.p = (const NPHC_RO double*)(A.Jpack);
+        gamma = {A.gamma[0], A.gamma[1]};
+        load_group_row<double, M>(C, r, G);
+    }
+    int64_t item = -1;
+    bool active = false, drained = false;
+    int post = 0;
+
+    for (;;) {
+        if (!drained) {
+            // the leader lane (r = 0) of every idle group asks for a path
+            const unsigned long long need = __ballot(!active && r == 0);
+            if (need) {
+                const int cnt = __popcll(need);
+                const int leader = __ffsll((long long)need) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&A.q->next[c], (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                if ((int64_t)(base + cnt) >= qhi) drained = true;
+                if (!active) {
+                    const int rank = __popcll(need & ((1ull << (grp * kGroup)) - 1ull));
+                    const int64_t qpos = (int64_t)base + rank;
+                    if (qpos < qhi) {
+                        item = A.ids ? A.ids[qpos] : qpos;
+                        int64_t pid;
+                        if (UNIFORM) {
+                            pid = item;
+                        } else {
+                            const int64_t sys = find_system(A.path_off, A.num_systems, item);
+                            pid = item - A.path_off[sys];
+                            C.p = (const NPHC_RO double*)(A.Jpack) + A.Jpack_off[sys];
+                            gamma = {A.gamma[2 * sys], A.gamma[2 * sys + 1]};
+                            load_group_row<double, M>(C, r, G);
+                        }
+                        if (A.o.resume) {
+                            read_path<Store, M>(A, item, S);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < M; ++k) {
+                                S.st.put(k, {((pid >> k) & 1) ? -1.0 : 1.0, 0.0});
+                                S.st.put(M + k, {((pid >> (M + k)) & 1) ? -1.0 : 1.0, 0.0});
+                            }
+                            S.t = 0.0;
+                            S.h = A.o.h0;
+                            S.acc = S.rej = S.solves = 0;
+                        }
+                        S.h_acc = S.h;
+                        {
+                            Point<double, M> zc;
+                            S.st.load_point(zc);
+                            S.znorm = norm_inf<double, M>(zc);
+                        }
+                        S.streak = S.rej_run = 0;
+                        S.status = NPHC_PATH_PENDING;
+                        post = 0;
+                        active = true;
+                    }
+                }
+            }
+        }
+        if (!__any(active)) break;
+        if (active) {
+            path_step<Store, M, GroupSolver<M>>(C, gamma, C, gamma, A.o, S, GroupSolver<M>{&G});
+            if (drained) ++post;
+            if (S.status == NPHC_PATH_PENDING && A.o.drain_steps > 0 && post >= A.o.drain_steps)
+                S.status = NPHC_PATH_HANDOFF;
+            if (S.status != NPHC_PATH_PENDING) {
+                if (r == 0) write_path<Store, M>(A, item, S);
+                active = false;
+            }
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void track_group_uniform_kernel(TrackArgs A)
+{
+    __shared__ cx<double> lds[(64 / kGroup) * 4 * M];
+    run_class_group<M, true>(A, 0, lds);
+}
+
+__global__ __launch_bounds__(64) void track_group_batch_kernel(TrackArgs A)
+{
+    __shared__ cx<double> lds[(64 / kGroup) * 4 * kBatchMaxM];
+    for (int c = 0; c < A.num_classes; ++c) {
+        switch (A.cls[c].M) {
+#define NPHC_CASE(m) \
+    case m: run_class_group<m, false>(A, c, lds); break;
+            NPHC_CASE(1) NPHC_CASE(2) NPHC_CASE(3) NPHC_CASE(4)
+            NPHC_CASE(5) NPHC_CASE(6) NPHC_CASE(7) NPHC_CASE(8)
+#undef NPHC_CASE
+            default: break;
         }
     }
 }
@@ -283,6 +404,9 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     if (o->max_corr < 1 || o->max_corr > 16 || o->max_steps < 1 || !(o->t_end > 0.0) ||
         o->t_end > 1.0 || !(o->h0 > 0.0) || !(o->hmax > 0.0) || (o->predictor != 0 && o->predictor != 1))
         return NPHC_EINVAL;
+    if ((o->lanes_per_path != 1 && o->lanes_per_path != kGroup) || o->drain_steps < 0) return NPHC_EINVAL;
+    const bool grouped = o->lanes_per_path == kGroup;
+    if (grouped && precision != NPHC_FP64) return NPHC_EUNSUPPORTED;
 
     char* base = static_cast<char*>(ws);
     TrackArgs A = {};
@@ -316,6 +440,7 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     A.o.handoff_steps = o->handoff_steps;
     A.o.pred_tol = o->pred_tol;
     A.o.step_ctrl = o->step_ctrl;
+    A.o.drain_steps = o->drain_steps;
     A.out_stride = item_stride;
     A.z = z;
     A.t = t;
@@ -355,7 +480,11 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     const void* fn = nullptr;
     if (!mixed) {
         switch (minN - 1) {
-#define NPHC_UCASE(m) case m: fn = reinterpret_cast<const void*>(&track_uniform_kernel<T, m>); break;
+#define NPHC_UCASE(m)                                                                 \
+    case m:                                                                           \
+        fn = grouped ? reinterpret_cast<const void*>(&track_group_uniform_kernel<m>) \
+                     : reinterpret_cast<const void*>(&track_uniform_kernel<T, m>);    \
+        break;
             NPHC_UCASE(1) NPHC_UCASE(2) NPHC_UCASE(3) NPHC_UCASE(4) NPHC_UCASE(5) NPHC_UCASE(6)
             NPHC_UCASE(7) NPHC_UCASE(8) NPHC_UCASE(9) NPHC_UCASE(10) NPHC_UCASE(11) NPHC_UCASE(12)
 #undef NPHC_UCASE
@@ -365,7 +494,8 @@ static int launch_track(const nphc_batch* b, const int64_t* ids, int64_t count,
     }
     if (!fn) {
         if (maxN > NPHC_BATCH_MAX_N) return NPHC_EUNSUPPORTED;
-        fn = reinterpret_cast<const void*>(&track_batch_kernel<T>);
+        fn = grouped ? reinterpret_cast<const void*>(&track_group_batch_kernel)
+                     : reinterpret_cast<const void*>(&track_batch_kernel<T>);
     }
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1)

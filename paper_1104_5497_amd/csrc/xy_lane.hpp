@@ -36,7 +36,7 @@ namespace nphc {
 // the fixed spin w_k = J_{k,N} at p[k*N + M].  Diagonal entries are never read.
 template <class T, int M>
 struct Couplings {
-    const T* p;
+    const NPHC_RO T* p;
     NPHC_HD T J(int k, int j) const { return p[k * (M + 1) + j]; }
     NPHC_HD T w(int k) const { return p[k * (M + 1) + M]; }
 };

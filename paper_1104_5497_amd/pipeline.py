@@ -162,13 +162,29 @@ class Options:
     classify: Optional[L.ClassOpts_] = None
     dup_tol: float = 1e-8
     retrack_rounds: int = 2
+    # Tails: once a launch's queue is empty, its paths in flight get at most
+    # this many more steps, then the lane-group tracker (16 lanes per path,
+    # float64) finishes them.  None: the default for the precision; 0: off.
+    # Which paths are still in flight then depends on scheduling, so such a
+    # path may finish in float64 in one run and in float32 in another (its
+    # endpoint then differs in the last bits; the certified sets do not).
+    # deterministic = True turns the drain hand-off off: every output is then
+    # a function of the path id alone.
+    drain: Optional[int] = None
+    cont_drain: int = 20          # the same for the per-lane float64 continuation
+    tail_group: bool = True
+    deterministic: bool = False
+
+
+DRAIN_DEFAULT = {"fp32": 96, "fp64": 112}
 
 
 def conservative_opts() -> L.TrackOpts_:
     """Re-tracking settings: float64, tight corrector, large divergence
-    radius, no end-zone shortcuts (the predictor-error guard stays on)."""
+    radius, no end-zone shortcuts (the predictor-error guard stays on); a lane
+    group per path, since only a few paths are re-tracked."""
     return L.default_track_opts(L.NPHC_FP64).copy(corr_tol=1e-10, R_inf=1e8, grow_cap=0.0,
-                                                   hmin_rel=0.0)
+                                                   hmin_rel=0.0, lanes_per_path=16)
 
 
 def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None, stream=None,
@@ -184,6 +200,9 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     s = _stream(stream)
     P = batch.num_items
     to = opts.track or L.default_track_opts(prec)
+    drain = DRAIN_DEFAULT[opts.precision] if opts.drain is None else opts.drain
+    if opts.track is None and opts.tail_group and not opts.deterministic:
+        to = to.copy(drain_steps=drain)
     co = opts.cert or L.default_cert_opts()
     clo = opts.classify or L.default_class_opts()
     rt = opts.retrack or conservative_opts()
@@ -204,9 +223,14 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
         events["track_end"].record()
     if "after_track" in events:
         events["after_track"]()
-    if to.handoff_rejects > 0 or to.handoff_norm > 0 or to.handoff_steps > 0:
-        # float64 continuation of the paths the float32 tracker handed off
-        ro = opts.resume or L.default_track_opts(L.NPHC_FP64).copy(resume=1)
+    handed_off = (to.handoff_rejects > 0 or to.handoff_norm > 0 or to.handoff_steps > 0 or
+                  to.drain_steps > 0)
+    if handed_off and prec == L.NPHC_FP32:
+        # float64 continuation of the paths the float32 tracker handed off,
+        # one path per lane (its own tail left to the lane groups below)
+        ro = opts.resume or L.default_track_opts(L.NPHC_FP64).copy(
+            resume=1,
+            drain_steps=opts.cont_drain if opts.tail_group and not opts.deterministic else 0)
         c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)   # counts[9]: handed off
         L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho, None, 0,
                                 s), "nphc_select")
@@ -218,6 +242,22 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
                                      b.ws64.numel(), s), "nphc_track_paths(resume)")
         if "resume_end" in events:
             events["resume_end"].record()
+    if "after_resume" in events:
+        events["after_resume"]()
+    if handed_off and opts.tail_group:
+        # the last, long paths: float64, a group of 16 lanes per path
+        go = L.default_track_opts(L.NPHC_FP64).copy(resume=1, lanes_per_path=16)
+        c_tail = ctypes.c_void_p(cnt.data_ptr() + 8 * 10)  # counts[10]: tail paths
+        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_tail, None,
+                                0, s), "nphc_select")
+        if "tail_begin" in events:
+            events["tail_begin"].record()
+        L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_tail, L.NPHC_FP64, ctypes.byref(go),
+                                     _p(b.z), stride, _p(b.t), _p(b.status), _p(b.accepted),
+                                     _p(b.rejected), _p(b.solves), _p(b.h), _p(b.ws64),
+                                     b.ws64.numel(), s), "nphc_track_paths(tail)")
+        if "tail_end" in events:
+            events["tail_end"].record()
     L.check(lib.nphc_refine_certify(B, None, P, None, ctypes.byref(co), _p(b.z), stride, _p(b.t),
                                     _p(b.status), _p(b.endpoint), _p(b.resid), _p(b.cond),
                                     _p(b.beta), _p(b.alpha), _p(b.alpha_real), s),

@@ -43,16 +43,21 @@ def test_batch384_matches_oracle(precision):
     _check(res, rings)
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("deterministic", [True, False])
+def test_graph_replay_matches_eager(deterministic):
     """Capture the whole pipeline once; every replay (with eager work and
-    synchronisation in between) reproduces the eager result exactly."""
+    synchronisation in between) reproduces the eager result: bit for bit in
+    deterministic mode; otherwise the same certified real sets, with at most
+    0.1% of the other endpoints classed differently (the drain hand-off of the
+    last paths depends on scheduling, and a path that finishes in float64
+    follows the float64 stopping rules)."""
     import torch
     from paper_1104_5497_amd import graph, pipeline
     rings = _golden()
     B = workload.batch_rings(0)
     sel = list(range(0, 384, 8))                 # 48 rings, sizes still mixed
     batch = pipeline.Batch([B.J[i] for i in sel], [B.gamma[i] for i in sel])
-    opts = pipeline.Options(precision="fp32")
+    opts = pipeline.Options(precision="fp32", deterministic=deterministic)
     eager = pipeline.allocate(batch, "fp32")
     pipeline.run(batch, opts, eager)
     ref = pipeline.collect(batch, eager)
@@ -65,9 +70,17 @@ def test_graph_replay_matches_eager():
         out = pipeline.collect(batch, b)
         for s, r in zip(out["systems"], ref["systems"]):
             assert np.array_equal(s.real_items, r.real_items)
-            assert np.array_equal(s.theta, r.theta)
             assert np.array_equal(s.index, r.index)
-        assert torch.equal(b.z, eager.z)
+            if deterministic:
+                assert np.array_equal(s.theta, r.theta)
+            else:
+                assert np.max(np.abs(s.theta - r.theta), initial=0.0) < 1e-12
+        if deterministic:
+            assert torch.equal(b.z, eager.z)
+        else:
+            differ = int((b.endpoint != eager.endpoint).sum())
+            print(f"replay {rep}: {differ} endpoint classes differ", flush=True)
+            assert differ <= 1e-3 * b.endpoint.numel()
     _check(out, [rings[i] for i in sel])
 
 

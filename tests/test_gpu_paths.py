@@ -84,3 +84,24 @@ def test_ring10_sampled_paths_match_oracle(precision):
     tr = sys_.track(gamma, ids)
     ep_o, _, _ = oracle._classify_endpoints(sys_, tr["z"], tr["t"], tr["status"], oracle.PostOpts())
     _compare(z_g[ids], ep_g[ids], tr["z"], ep_o, ids)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_lane_group_tracker_matches_oracle(case):
+    """The float64 tracker with a group of 16 lanes per path (used for the
+    last, long paths of a launch and for re-tracks) run on every path from
+    t = 0: each path ends at the oracle's root."""
+    import torch
+    from paper_1104_5497_amd import _lib as L, pipeline
+    kind, N, p, js = case
+    print(f"lane-group per-path {case}", flush=True)
+    J = _J(kind, N, p, js)
+    ref = _oracle_full(kind, N, p, js)
+    batch = pipeline.Batch([J], [workload.gamma_from_seed(0)])
+    to = L.default_track_opts(L.NPHC_FP64).copy(lanes_per_path=16)
+    b = pipeline.run(batch, pipeline.Options(precision="fp64", track=to, tail_group=False))
+    torch.cuda.synchronize()
+    n = 2 * (N - 1)
+    zp = b.z.cpu().numpy()
+    z = (zp[0:2 * n:2] + 1j * zp[1:2 * n:2]).T
+    _compare(z, b.endpoint.cpu().numpy(), ref.z, ref.endpoint)
