@@ -257,7 +257,9 @@ size_t nphc_duplicates_workspace_size(int64_t count);
  * Ordered compaction: writes, in increasing order, every item id g in
  * [0, num_items) with (1 << code[g]) & mask != 0 to out_ids (device) and
  * their number to *out_count (device int64).  out_ids needs num_items
- * entries.
+ * entries.  With a workspace of nphc_select_workspace_size(num_items) bytes
+ * (device, 8-byte aligned) the work is spread over many workgroups; with
+ * workspace == NULL one workgroup does it.
  */
 int nphc_select(const int32_t* code, int64_t num_items, uint64_t mask, int64_t* out_ids,
                 int64_t* out_count, void* workspace, size_t ws_bytes, hipStream_t stream);

@@ -20,10 +20,12 @@
 // constant address space lets wave-uniform reads use scalar loads into SGPRs
 // instead of vector loads into VGPRs.  Divergent addresses still work (they
 // become vector loads).
+#ifndef NPHC_RO
 #if defined(__HIP_DEVICE_COMPILE__)
 #define NPHC_RO __attribute__((address_space(4)))
 #else
 #define NPHC_RO
+#endif
 #endif
 
 namespace nphc {

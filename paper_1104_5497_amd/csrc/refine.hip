@@ -80,8 +80,8 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
     for (int64_t pos = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; pos < hi; pos += step) {
         const int64_t g = A.ids ? A.ids[pos] : pos;
         const int64_t sys = find_system(A.path_off, A.num_systems, g);
-        Couplings<double, M> C;
-        C.p = (const NPHC_RO double*)(A.J + A.J_off[sys]);
+        CouplingsG<double, M> C;
+        C.p = A.J + A.J_off[sys];
         Point<double, M> z;
 #pragma unroll
         for (int k = 0; k < M; ++k) {

@@ -37,22 +37,125 @@ __global__ __launch_bounds__(1024) void select_kernel(const int32_t* code, int64
     if (tid == 1023) *out_count = cnt[1023];
 }
 
+// Multi-block version (with workspace): block b owns the contiguous tile
+// [b * tile, (b + 1) * tile) of the items.  Pass 1 counts each tile's
+// matches, pass 2 turns the counts into tile offsets (one block), pass 3
+// writes every tile's matches in order: 256 items at a time, the position of
+// a match from a ballot within its wave plus the counts of the waves before.
+constexpr int kSelThreads = 256;
+constexpr int kSelMaxBlocks = 1024;
+
+__device__ __forceinline__ bool sel_match(const int32_t* code, int64_t i, uint64_t mask)
+{
+    const int32_t v = code[i];
+    return v >= 0 && v < 64 && ((mask >> v) & 1ull);
+}
+
+__global__ __launch_bounds__(kSelThreads) void select_count_kernel(const int32_t* code, int64_t n,
+                                                                   uint64_t mask, int64_t tile,
+                                                                   int64_t* counts)
+{
+    __shared__ int64_t part[kSelThreads / 64];
+    const int64_t b0 = int64_t(blockIdx.x) * tile;
+    const int64_t e0 = min(n, b0 + tile);
+    int64_t c = 0;
+    for (int64_t i = b0 + threadIdx.x; i < e0; i += kSelThreads) c += sel_match(code, i, mask) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (__lane_id() == 0) part[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kSelThreads / 64; ++w) t += part[w];
+        counts[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of the block counts in place; the total to *out_count
+__global__ __launch_bounds__(kSelMaxBlocks) void select_scan_kernel(int64_t* counts, int nblocks,
+                                                                    int64_t* out_count)
+{
+    __shared__ int64_t s[kSelMaxBlocks];
+    const int t = threadIdx.x;
+    const int64_t mine = t < nblocks ? counts[t] : 0;
+    s[t] = mine;
+    __syncthreads();
+    for (int off = 1; off < kSelMaxBlocks; off <<= 1) {
+        const int64_t add = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    if (t < nblocks) counts[t] = s[t] - mine;
+    if (t == kSelMaxBlocks - 1) *out_count = s[t];
+}
+
+__global__ __launch_bounds__(kSelThreads) void select_write_kernel(const int32_t* code, int64_t n,
+                                                                   uint64_t mask, int64_t tile,
+                                                                   const int64_t* offsets,
+                                                                   int64_t* out)
+{
+    __shared__ int64_t wsum[kSelThreads / 64];
+    const int64_t b0 = int64_t(blockIdx.x) * tile;
+    const int64_t e0 = min(n, b0 + tile);
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    int64_t base = offsets[blockIdx.x];
+    for (int64_t c0 = b0; c0 < e0; c0 += kSelThreads) {
+        const int64_t i = c0 + threadIdx.x;
+        const bool m = i < e0 && sel_match(code, i, mask);
+        const unsigned long long bal = __ballot(m);
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int64_t before = 0, total = 0;
+        for (int w = 0; w < kSelThreads / 64; ++w) {
+            before += w < wave ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        if (m) out[base + before + __popcll(bal & ((1ull << lane) - 1ull))] = i;
+        base += total;
+        __syncthreads();
+    }
+}
+
+static int select_blocks(int64_t n, int64_t* tile)
+{
+    int64_t nb = (n + kSelThreads - 1) / kSelThreads;
+    if (nb > kSelMaxBlocks) nb = kSelMaxBlocks;
+    if (nb < 1) nb = 1;
+    *tile = (n + nb - 1) / nb;
+    if (*tile < 1) *tile = 1;
+    return int(nb);
+}
+
 }  // namespace nphc
 
 extern "C" size_t nphc_select_workspace_size(int64_t num_items)
 {
-    (void)num_items;
-    return 0;
+    if (num_items < 0) return 0;
+    int64_t tile;
+    return size_t(nphc::select_blocks(num_items, &tile)) * sizeof(int64_t);
 }
 
 extern "C" int nphc_select(const int32_t* code, int64_t num_items, uint64_t mask, int64_t* out_ids,
                            int64_t* out_count, void* workspace, size_t ws_bytes, hipStream_t stream)
 {
-    (void)workspace;
-    (void)ws_bytes;
     if (!code || !out_ids || !out_count || num_items < 0) return NPHC_EINVAL;
-    hipLaunchKernelGGL(nphc::select_kernel, dim3(1), dim3(1024), 0, stream, code, num_items, mask,
-                       out_ids, out_count);
+    if (!workspace) {
+        hipLaunchKernelGGL(nphc::select_kernel, dim3(1), dim3(1024), 0, stream, code, num_items,
+                           mask, out_ids, out_count);
+        if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
+        return NPHC_OK;
+    }
+    int64_t tile;
+    const int nb = nphc::select_blocks(num_items, &tile);
+    if (ws_bytes < size_t(nb) * sizeof(int64_t) || (reinterpret_cast<uintptr_t>(workspace) & 7))
+        return NPHC_EWORKSPACE;
+    int64_t* counts = static_cast<int64_t*>(workspace);
+    hipLaunchKernelGGL(nphc::select_count_kernel, dim3(nb), dim3(nphc::kSelThreads), 0, stream,
+                       code, num_items, mask, tile, counts);
+    hipLaunchKernelGGL(nphc::select_scan_kernel, dim3(1), dim3(nphc::kSelMaxBlocks), 0, stream,
+                       counts, nb, out_count);
+    hipLaunchKernelGGL(nphc::select_write_kernel, dim3(nb), dim3(nphc::kSelThreads), 0, stream,
+                       code, num_items, mask, tile, counts, out_ids);
     if (hipGetLastError() != hipSuccess) return NPHC_EHIP;
     return NPHC_OK;
 }

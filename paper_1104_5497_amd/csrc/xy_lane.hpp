@@ -41,6 +41,16 @@ struct Couplings {
     NPHC_HD T w(int k) const { return p[k * (M + 1) + M]; }
 };
 
+// The same view through a generic pointer, for couplings whose address
+// differs between lanes (the constant address space only pays for
+// wave-uniform reads).
+template <class T, int M>
+struct CouplingsG {
+    const T* p;
+    NPHC_HD T J(int k, int j) const { return p[k * (M + 1) + j]; }
+    NPHC_HD T w(int k) const { return p[k * (M + 1) + M]; }
+};
+
 template <class T, int M>
 struct Point {
     cx<T> x[M], y[M];
@@ -97,8 +107,8 @@ struct UnitRhs {
 // Rhs::kExt: the right-hand side is supplied by rhs (rg(k): gradient row k,
 // rc(k): constraint row k), e.g. -H evaluated in a wider type; H_z is still
 // formed from z in type T.
-template <class T, int M, class Rhs = OwnRhs>
-NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool newton,
+template <class T, int M, class Rhs = OwnRhs, class Cp = Couplings<T, M>>
+NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
                         const Point<T, M>& z, Point<T, M>& d, const Rhs& rhs = Rhs{})
 {
     const cx<T> g = omt * gamma;             // (1 - t) gamma
@@ -240,8 +250,8 @@ NPHC_HD bool solve_step(const Couplings<T, M>& C, cx<T> gamma, T t, T omt, bool 
 }
 
 // The target system F(z) (t = 1): F.x[k] gradient row k, F.y[k] constraint row k.
-template <class T, int M>
-NPHC_HD void eval_F(const Couplings<T, M>& C, const Point<T, M>& z, Point<T, M>& F)
+template <class T, int M, class Cp = Couplings<T, M>>
+NPHC_HD void eval_F(const Cp& C, const Point<T, M>& z, Point<T, M>& F)
 {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -260,8 +270,8 @@ NPHC_HD void eval_F(const Couplings<T, M>& C, const Point<T, M>& z, Point<T, M>&
 
 // ||F_z(z)||_F^2.  Gradient row k: dF_k/dx_j = J_kj y_k, dF_k/dy_j = -J_kj x_k
 // (j != k), dF_k/dx_k = -Sy_k, dF_k/dy_k = Sx_k; constraint row k: 2 x_k, 2 y_k.
-template <class T, int M>
-NPHC_HD T jac_frob2(const Couplings<T, M>& C, const Point<T, M>& z)
+template <class T, int M, class Cp = Couplings<T, M>>
+NPHC_HD T jac_frob2(const Cp& C, const Point<T, M>& z)
 {
     T s = T(0);
 #pragma unroll

@@ -111,6 +111,7 @@ class Buffers:
     ws: torch.Tensor           # tracker workspace (uint8)
     ws64: torch.Tensor         # tracker workspace for float64 re-tracking
     wsdup: torch.Tensor        # duplicate-check hash table
+    wssel: torch.Tensor        # compaction block counts
     # classification outputs, per candidate position
     is_real: torch.Tensor
     theta: torch.Tensor
@@ -139,6 +140,8 @@ def allocate(batch: Batch, precision: str) -> Buffers:
         ws=torch.zeros(max(int(ws_bytes), 256), dtype=torch.uint8, device=dev),
         ws64=torch.zeros(max(int(ws64_bytes), 256), dtype=torch.uint8, device=dev),
         wsdup=torch.zeros(max(int(L.lib().nphc_duplicates_workspace_size(P)), 256),
+                          dtype=torch.uint8, device=dev),
+        wssel=torch.zeros(max(int(L.lib().nphc_select_workspace_size(P)), 256),
                           dtype=torch.uint8, device=dev),
         is_real=torch.zeros(P, **i32), theta=torch.zeros((m, P), **f64),
         energy=torch.zeros(P, **f64), index=torch.zeros(P, **i32),
@@ -232,8 +235,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
             resume=1,
             drain_steps=opts.cont_drain if opts.tail_group and not opts.deterministic else 0)
         c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)   # counts[9]: handed off
-        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho, None, 0,
-                                s), "nphc_select")
+        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho,
+                                _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         if "resume_begin" in events:
             events["resume_begin"].record()
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_ho, L.NPHC_FP64, ctypes.byref(ro),
@@ -248,8 +251,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
         # the last, long paths: float64, a group of 16 lanes per path
         go = L.default_track_opts(L.NPHC_FP64).copy(resume=1, lanes_per_path=16)
         c_tail = ctypes.c_void_p(cnt.data_ptr() + 8 * 10)  # counts[10]: tail paths
-        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_tail, None,
-                                0, s), "nphc_select")
+        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_tail,
+                                _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         if "tail_begin" in events:
             events["tail_begin"].record()
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_tail, L.NPHC_FP64, ctypes.byref(go),
@@ -265,7 +268,7 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
 
     def dedupe(probe=None, c_probe=None):
         L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_NONSINGULAR), _p(b.ids2), c_sel,
-                                None, 0, s), "nphc_select")
+                                _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         L.check(lib.nphc_mark_duplicates(B, _p(b.ids2), P, c_sel, _p(probe), c_probe,
                                          opts.dup_tol, _p(b.z), stride, _p(b.endpoint), c_dup,
                                          _p(b.wsdup), b.wsdup.numel(), s),
@@ -278,7 +281,7 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
         o = rt.copy(h0=min(rt.h0, hmax), hmax=hmax)
         c_rt = ctypes.c_void_p(cnt.data_ptr() + 8 * (2 + r))  # counts[2+r]: re-tracked
         L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_FAIL, L.END_DUPLICATE), _p(b.ids),
-                                c_rt, None, 0, s), "nphc_select")
+                                c_rt, _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_rt, L.NPHC_FP64, ctypes.byref(o), _p(b.z),
                                      stride, _p(b.t), _p(b.status), _p(b.accepted),
                                      _p(b.rejected), None, _p(b.h), _p(b.ws64), b.ws64.numel(), s),
@@ -291,8 +294,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
         dedupe(b.ids, c_rt)
     # classification of every nonsingular endpoint (the real filter is inside)
     c_cls = ctypes.c_void_p(cnt.data_ptr() + 8 * 8)       # counts[8]: nonsingular endpoints
-    L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_NONSINGULAR), _p(b.ids2), c_cls, None,
-                            0, s), "nphc_select")
+    L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_NONSINGULAR), _p(b.ids2), c_cls,
+                            _p(b.wssel), b.wssel.numel(), s), "nphc_select")
     L.check(lib.nphc_classify(B, _p(b.ids2), P, c_cls, ctypes.byref(clo), co.real_tol, _p(b.z),
                               stride, _p(b.endpoint), _p(b.alpha_real), _p(b.is_real),
                               _p(b.theta), _p(b.energy), _p(b.index), _p(b.eig),
