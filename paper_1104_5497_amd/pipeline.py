@@ -107,6 +107,8 @@ class Buffers:
     alpha_real: torch.Tensor
     ids: torch.Tensor          # id list scratch
     ids2: torch.Tensor
+    ids3: torch.Tensor         # paths finished by the main launch (overlapped refinement)
+    ids4: torch.Tensor         # paths left to the lane-group tail
     counts: torch.Tensor       # small device counters (int64)
     ws: torch.Tensor           # tracker workspace (uint8)
     ws64: torch.Tensor         # tracker workspace for float64 re-tracking
@@ -119,6 +121,7 @@ class Buffers:
     index: torch.Tensor
     eig: torch.Tensor
     degenerate: torch.Tensor
+    side: Optional[object] = None   # second stream (created on first use)
 
 
 def allocate(batch: Batch, precision: str) -> Buffers:
@@ -136,7 +139,8 @@ def allocate(batch: Batch, precision: str) -> Buffers:
         endpoint=torch.zeros(P, **i32),
         resid=torch.zeros(P, **f64), cond=torch.zeros(P, **f64), beta=torch.zeros(P, **f64),
         alpha=torch.zeros(P, **f64), alpha_real=torch.zeros(P, **f64),
-        ids=torch.zeros(P, **i64), ids2=torch.zeros(P, **i64), counts=torch.zeros(16, **i64),
+        ids=torch.zeros(P, **i64), ids2=torch.zeros(P, **i64), ids3=torch.zeros(P, **i64),
+        ids4=torch.zeros(P, **i64), counts=torch.zeros(16, **i64),
         ws=torch.zeros(max(int(ws_bytes), 256), dtype=torch.uint8, device=dev),
         ws64=torch.zeros(max(int(ws64_bytes), 256), dtype=torch.uint8, device=dev),
         wsdup=torch.zeros(max(int(L.lib().nphc_duplicates_workspace_size(P)), 256),
@@ -177,6 +181,9 @@ class Options:
     cont_drain: int = 20          # the same for the per-lane float64 continuation
     tail_group: bool = True
     deterministic: bool = False
+    # refine the paths the main launch finished on a second stream while the
+    # float64 continuation and tail run (they touch disjoint items)
+    overlap: bool = True
 
 
 DRAIN_DEFAULT = {"fp32": 96, "fp64": 112}
@@ -201,6 +208,7 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     prec = PREC[opts.precision]
     b = bufs or allocate(batch, opts.precision)
     s = _stream(stream)
+    main = stream if stream is not None else torch.cuda.current_stream()
     P = batch.num_items
     to = opts.track or L.default_track_opts(prec)
     drain = DRAIN_DEFAULT[opts.precision] if opts.drain is None else opts.drain
@@ -228,15 +236,40 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
         events["after_track"]()
     handed_off = (to.handoff_rejects > 0 or to.handoff_norm > 0 or to.handoff_steps > 0 or
                   to.drain_steps > 0)
+    c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)       # counts[9]: handed off
+    overlap = handed_off and opts.overlap
+
+    def refine(ids, c_list, strm):
+        L.check(lib.nphc_refine_certify(B, _p(ids), P, c_list, ctypes.byref(co), _p(b.z), stride,
+                                        _p(b.t), _p(b.status), _p(b.endpoint), _p(b.resid),
+                                        _p(b.cond), _p(b.beta), _p(b.alpha), _p(b.alpha_real),
+                                        strm), "nphc_refine_certify")
+
+    if handed_off:
+        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho,
+                                _p(b.wssel), b.wssel.numel(), s), "nphc_select")
+    if overlap:
+        # the paths the main launch finished are refined on a second stream
+        c_fin = ctypes.c_void_p(cnt.data_ptr() + 8 * 11)  # counts[11]: finished
+        L.check(lib.nphc_select(_p(b.status), P,
+                                _mask(L.PATH_REACHED, L.PATH_DIVERGED, L.PATH_FAIL_MINSTEP,
+                                      L.PATH_FAIL_MAXSTEPS, L.PATH_FAIL_NONFINITE,
+                                      L.PATH_STALLED),
+                                _p(b.ids3), c_fin, _p(b.wssel), b.wssel.numel(), s), "nphc_select")
+        if b.side is None:
+            b.side = torch.cuda.Stream(device=b.z.device)
+        fork = torch.cuda.Event()
+        fork.record(main)
+        b.side.wait_event(fork)
+        refine(b.ids3, c_fin, ctypes.c_void_p(b.side.cuda_stream))
+        join = torch.cuda.Event()
+        join.record(b.side)
     if handed_off and prec == L.NPHC_FP32:
         # float64 continuation of the paths the float32 tracker handed off,
         # one path per lane (its own tail left to the lane groups below)
         ro = opts.resume or L.default_track_opts(L.NPHC_FP64).copy(
             resume=1,
             drain_steps=opts.cont_drain if opts.tail_group and not opts.deterministic else 0)
-        c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)   # counts[9]: handed off
-        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_ho,
-                                _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         if "resume_begin" in events:
             events["resume_begin"].record()
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_ho, L.NPHC_FP64, ctypes.byref(ro),
@@ -251,20 +284,25 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
         # the last, long paths: float64, a group of 16 lanes per path
         go = L.default_track_opts(L.NPHC_FP64).copy(resume=1, lanes_per_path=16)
         c_tail = ctypes.c_void_p(cnt.data_ptr() + 8 * 10)  # counts[10]: tail paths
-        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids), c_tail,
+        L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids4), c_tail,
                                 _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         if "tail_begin" in events:
             events["tail_begin"].record()
-        L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_tail, L.NPHC_FP64, ctypes.byref(go),
+        L.check(lib.nphc_track_paths(B, _p(b.ids4), P, c_tail, L.NPHC_FP64, ctypes.byref(go),
                                      _p(b.z), stride, _p(b.t), _p(b.status), _p(b.accepted),
                                      _p(b.rejected), _p(b.solves), _p(b.h), _p(b.ws64),
                                      b.ws64.numel(), s), "nphc_track_paths(tail)")
         if "tail_end" in events:
             events["tail_end"].record()
-    L.check(lib.nphc_refine_certify(B, None, P, None, ctypes.byref(co), _p(b.z), stride, _p(b.t),
-                                    _p(b.status), _p(b.endpoint), _p(b.resid), _p(b.cond),
-                                    _p(b.beta), _p(b.alpha), _p(b.alpha_real), s),
-            "nphc_refine_certify")
+    if overlap:
+        # the handed-off paths, once finished; then wait for the other half
+        refine(b.ids, c_ho, s)
+        main.wait_event(join)
+    else:
+        L.check(lib.nphc_refine_certify(B, None, P, None, ctypes.byref(co), _p(b.z), stride,
+                                        _p(b.t), _p(b.status), _p(b.endpoint), _p(b.resid),
+                                        _p(b.cond), _p(b.beta), _p(b.alpha), _p(b.alpha_real), s),
+                "nphc_refine_certify")
 
     def dedupe(probe=None, c_probe=None):
         L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_NONSINGULAR), _p(b.ids2), c_sel,
