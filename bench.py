@@ -57,8 +57,8 @@ FP64_VECTOR_PEAK = 78.6    # TFLOP/s, MI355X vector fp64 (AMD spec)
 # tracker sources it was measured on: reported as null once they change.
 TRACKER_SOURCES = ("track.hip", "path.hpp", "xy_lane.hpp", "cx.hpp", "common.hpp")
 MEASURED_TRAFFIC = dict(
-    sources_sha256="2ecf3f59f005cca781bb939bf4fb3d3a7b2762f690ede2fa0f3101b9a5d0b52b",
-    fetch_kib=3373.25, fetch_scale=1.99974, write_kib=367882.78125, write_scale=1.0)
+    sources_sha256="b122e7662fb99141c57a49f0a7c55ae1d807009bc0207fb17951b338ff106a67",
+    fetch_kib=83163.375, fetch_scale=1.99969, write_kib=529577.78125, write_scale=1.0)
 
 
 def fetch_real(b):
