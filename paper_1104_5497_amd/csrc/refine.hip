@@ -35,6 +35,7 @@ struct RefineArgs {
 template <int M>
 struct RefineRhs {
     static constexpr bool kExt = true;
+    NPHC_HD bool use() const { return true; }
     int j;
     const Point<double, M>* F;
     template <class T> NPHC_HD cx<T> rg(int k) const

@@ -60,20 +60,16 @@ struct Point {
 // and the minimum-norm particular solution (px_k, py_k) of
 // a_k dx_k + b_k dy_k = s_k, where s_k is the row's right-hand side
 // -(c1 (y_k^2 - 1) + c2 (x_k^2 + y_k^2 - 1)).
-// With EXT the right-hand side s_ext is given instead.
+// With EXT the right-hand side s_ext is given instead, where use_ext holds.
 template <class T, bool EXT = false>
 NPHC_HD void constraint_row(T t, cx<T> gt, cx<T> c1, T c2, cx<T> x, cx<T> y, cx<T>& a, cx<T>& b,
-                            cx<T>& px, cx<T>& py, cx<T> s_ext = cx<T>{})
+                            cx<T>& px, cx<T>& py, cx<T> s_ext = cx<T>{}, bool use_ext = true)
 {
-    cx<T> s;
-    if constexpr (EXT) {
-        s = s_ext;
-    } else {
-        const cx<T> xx = x * x, yy = y * y;
-        const cx<T> ym1 = {yy.re - T(1), yy.im};
-        const cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
-        s = -(c1 * ym1 + c2 * con);
-    }
+    const cx<T> xx = x * x, yy = y * y;
+    const cx<T> ym1 = {yy.re - T(1), yy.im};
+    const cx<T> con = {xx.re + yy.re - T(1), xx.im + yy.im};
+    cx<T> s = -(c1 * ym1 + c2 * con);
+    if constexpr (EXT) s = use_ext ? s_ext : s;
     a = (T(2) * t) * x;
     b = T(2) * (gt * y);
     const cx<T> sk = s * rrcp(norm2(a) + norm2(b));
@@ -81,9 +77,13 @@ NPHC_HD void constraint_row(T t, cx<T> gt, cx<T> c1, T c2, cx<T> x, cx<T> y, cx<
     py = sk * conj(b);
 }
 
+// Right-hand side policies of solve_step.  kExt: the policy may supply the
+// right-hand side (rg, rc); use(): whether it does for this call (a runtime
+// choice lets one inlined solve serve both kinds of call).
 // Right-hand side computed inside the solve (from z, in the solve's type).
 struct OwnRhs {
     static constexpr bool kExt = false;
+    NPHC_HD bool use() const { return false; }
     template <class T> NPHC_HD cx<T> rg(int) const { return cx<T>{}; }
     template <class T> NPHC_HD cx<T> rc(int) const { return cx<T>{}; }
 };
@@ -94,6 +94,7 @@ template <int M>
 struct UnitRhs {
     static constexpr bool kExt = true;
     int j;
+    NPHC_HD bool use() const { return true; }
     template <class T> NPHC_HD cx<T> rg(int k) const { return {k == j ? T(1) : T(0), T(0)}; }
     template <class T> NPHC_HD cx<T> rc(int k) const { return {M + k == j ? T(1) : T(0), T(0)}; }
 };
@@ -126,7 +127,7 @@ NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
         for (int j = 0; j < M; ++j) {
             cx<T> aj, bj;
             constraint_row<T, Rhs::kExt>(t, gt, c1, c2, z.x[j], z.y[j], aj, bj, px[j], py[j],
-                                         rhs.template rc<T>(j));
+                                         rhs.template rc<T>(j), rhs.use());
         }
 #pragma unroll
         for (int k = 0; k < M; ++k) {
@@ -145,9 +146,8 @@ NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
             const cx<T> F = yk * sx - xk * sy;
             const cx<T> xx = xk * xk;
             const cx<T> xm1 = {xx.re - T(1), xx.im};
-            cx<T> rk;
-            if constexpr (Rhs::kExt) rk = rhs.template rg<T>(k);
-            else rk = -(c1 * xm1 + c2 * F);
+            cx<T> rk = -(c1 * xm1 + c2 * F);
+            if constexpr (Rhs::kExt) rk = rhs.use() ? rhs.template rg<T>(k) : rk;
             const cx<T> ak = (T(2) * t) * xk;
             const cx<T> bk = T(2) * (gt * yk);
             const cx<T> Akk = (T(2) * g) * xk - t * sy;
@@ -240,7 +240,7 @@ NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
     for (int k = 0; k < M; ++k) {
         cx<T> ak, bk, pxk, pyk;
         constraint_row<T, Rhs::kExt>(t, gt, c1, c2, z.x[k], z.y[k], ak, bk, pxk, pyk,
-                                     rhs.template rc<T>(k));
+                                     rhs.template rc<T>(k), rhs.use());
         d.x[k] = fma(bk, v[k], pxk);
         d.y[k] = fnma(ak, v[k], pyk);
         mag = fmax(mag, fmax(absmax(d.x[k]), absmax(d.y[k])));
