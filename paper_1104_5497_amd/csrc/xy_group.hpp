@@ -62,6 +62,44 @@ __device__ __forceinline__ cx<T> blend(bool c, cx<T> a, cx<T> b)
     return {blend(c, a.re, b.re), blend(c, a.im, b.im)};
 }
 
+// Butterfly exchange inside a DPP row (16 lanes, which is one group):
+// quad permutations [1,0,3,2] and [2,3,0,1] (partners lane ^ 1, lane ^ 2),
+// then the half-row mirror (lane i of 8 reads 7 - i) and the row mirror
+// (lane i of 16 reads 15 - i).  After the four stages a commutative,
+// associative combine has seen all 16 lanes.  The partner is always inside
+// the row, so no bound control is needed.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_x(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)u);
+    const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_x(float v)
+{
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+// one stage of the group argmax: largest val, ties to the lower lane
+template <int CTRL, class T>
+__device__ __forceinline__ void argmax_stage(T& val, int& who)
+{
+    const T v2 = dpp_x<CTRL>(val);
+    const int w2 = dpp_i<CTRL>(who);
+    const bool take = (v2 > val) || (v2 == val && w2 < who);
+    val = take ? v2 : val;
+    who = take ? w2 : who;
+}
+
 // a[r] for the lane's row r (bit r of sel set)
 template <class T, int M>
 __device__ __forceinline__ cx<T> pick(const cx<T> (&a)[M], unsigned sel)
@@ -125,14 +163,10 @@ __device__ __forceinline__ bool group_solve_step(const GroupRow<T, M>& G, cx<T> 
     for (int k = 0; k < M; ++k) {
         T val = blend(used, T(-1), abs1(R[k]));
         int who = r;
-#pragma unroll
-        for (int o = kGroup / 2; o > 0; o >>= 1) {
-            const T v2 = __shfl_xor(val, o, kGroup);
-            const int w2 = __shfl_xor(who, o, kGroup);
-            const bool take = (v2 > val) || (v2 == val && w2 < who);
-            val = take ? v2 : val;
-            who = take ? w2 : who;
-        }
+        argmax_stage<kDppXor1>(val, who);
+        argmax_stage<kDppXor2>(val, who);
+        argmax_stage<kDppHalfMirror>(val, who);
+        argmax_stage<kDppMirror>(val, who);
         const int p = who;
         piv[k] = p;
         ok = ok && (val > T(0));
