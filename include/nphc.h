@@ -111,7 +111,7 @@ typedef struct nphc_track_opts {
     double R_inf;     /* the path diverges when ||z||_inf > R_inf */
     double t_stall;   /* a step-size underflow at t >= t_stall is a stall near t = 1 */
     double t_end;     /* track t from 0 to t_end (1 for the whole homotopy) */
-    int32_t max_corr; /* Newton iterations per step */
+    int32_t max_corr; /* Newton iterations per step (default 2 for float32, 3 for float64) */
     int32_t max_steps;/* accepted + rejected steps */
     int32_t predictor;/* 0: classical RK4, 1: Euler (the paper's predictor) */
     int32_t resume;   /* 1: continue each selected path from its saved z, t, h and step counts */

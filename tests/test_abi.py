@@ -39,5 +39,6 @@ def test_host_only_calls():
     assert L.lib().nphc_strerror(L.NPHC_EINVAL) == b"invalid argument"
     o = L.default_track_opts(L.NPHC_FP64)
     assert o.max_corr == 3 and o.hmax == 0.05
+    assert L.default_track_opts(L.NPHC_FP32).max_corr == 2
     c = L.default_cert_opts()
     assert c.real_tol == 1e-7
