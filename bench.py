@@ -62,12 +62,17 @@ MEASURED_TRAFFIC = dict(
 
 
 def fetch_real(b):
-    """Compact results to the host: counts, then the classified candidates."""
-    counts = b.counts.cpu()
-    K = int(counts[8])
-    return dict(K=K, is_real=b.is_real[:K].cpu(), index=b.index[:K].cpu(),
-                theta=b.theta[:, :K].cpu(), energy=b.energy[:K].cpu(),
-                degenerate=b.degenerate[:K].cpu())
+    """Compact results to the host: the candidate count, then the classified
+    candidates packed into one float64 buffer (one copy; integers and flags
+    are exact in float64)."""
+    import torch
+    K = int(b.counts[8].item())
+    m = b.theta.shape[0]
+    packed = torch.cat([b.is_real[:K].double(), b.index[:K].double(), b.energy[:K],
+                        b.degenerate[:K].double(), b.theta[:, :K].reshape(-1)]).cpu()
+    return dict(K=K, is_real=packed[0:K].to(torch.int32), index=packed[K:2 * K].to(torch.int32),
+                energy=packed[2 * K:3 * K], degenerate=packed[3 * K:4 * K].to(torch.int32),
+                theta=packed[4 * K:].reshape(m, K))
 
 
 def time_pipeline(pipeline, batch, precision, steps, warmup):

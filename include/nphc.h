@@ -266,6 +266,20 @@ int nphc_select(const int32_t* code, int64_t num_items, uint64_t mask, int64_t* 
 size_t nphc_select_workspace_size(int64_t num_items);
 
 /*
+ * The same compaction over an id list: writes, in list order, every ids[i]
+ * (i < count, or i < min(count, *count_dev) when count_dev is non-NULL) with
+ * (1 << code[ids[i]]) & mask != 0 to out_ids and their number to *out_count.
+ * The pipeline uses it to split a list of handed-off paths into those a
+ * continuation finished and those still handed off.  ids, count_dev, out_ids
+ * and out_count are device memory; out_ids needs count entries and must not
+ * overlap ids.  The workspace is nphc_select_workspace_size(count) bytes (or
+ * NULL: one workgroup).  Every ids[i] must be a valid index into code.
+ */
+int nphc_select_list(const int32_t* code, const int64_t* ids, int64_t count,
+                     const int64_t* count_dev, uint64_t mask, int64_t* out_ids,
+                     int64_t* out_count, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Real filter and classification of the listed items (paper: a solution is
  * real when every |Im z_k| <= Delta_R; theta_k = atan2(y_k, x_k) in
  * (-pi, pi]; the stationary point is classified by the number of negative

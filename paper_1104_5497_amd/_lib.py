@@ -25,7 +25,7 @@ EXPORTS = [
     "nphc_default_track_opts", "nphc_default_cert_opts", "nphc_default_class_opts",
     "nphc_track_workspace_size", "nphc_track_paths", "nphc_refine_certify",
     "nphc_mark_duplicates", "nphc_duplicates_workspace_size", "nphc_select",
-    "nphc_select_workspace_size", "nphc_classify",
+    "nphc_select_list", "nphc_select_workspace_size", "nphc_classify",
     "nphc_adjoint", "nphc_strerror", "nphc_version",
 ]
 
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
     L.nphc_duplicates_workspace_size.argtypes = [i64]
     L.nphc_duplicates_workspace_size.restype = sz
     L.nphc_select.argtypes = [vp, i64, u64, vp, vp, vp, sz, vp]
+    L.nphc_select_list.argtypes = [vp, vp, i64, vp, u64, vp, vp, vp, sz, vp]
     L.nphc_select_workspace_size.argtypes = [i64]
     L.nphc_select_workspace_size.restype = sz
     L.nphc_classify.argtypes = [pB, vp, i64, vp, ctypes.POINTER(ClassOpts_), dbl, vp, i64, vp, vp,
@@ -116,7 +117,7 @@ def lib() -> ctypes.CDLL:
     L.nphc_version.argtypes = []
     L.nphc_version.restype = ctypes.c_char_p
     for f in ("nphc_track_paths", "nphc_refine_certify", "nphc_mark_duplicates", "nphc_select",
-              "nphc_classify", "nphc_adjoint"):
+              "nphc_select_list", "nphc_classify", "nphc_adjoint"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

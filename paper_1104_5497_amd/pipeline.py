@@ -109,6 +109,7 @@ class Buffers:
     ids2: torch.Tensor
     ids3: torch.Tensor         # paths finished by the main launch (overlapped refinement)
     ids4: torch.Tensor         # paths left to the lane-group tail
+    ids5: torch.Tensor         # handed-off paths the float64 continuation finished
     counts: torch.Tensor       # small device counters (int64)
     ws: torch.Tensor           # tracker workspace (uint8)
     ws64: torch.Tensor         # tracker workspace for float64 re-tracking
@@ -140,7 +141,7 @@ def allocate(batch: Batch, precision: str) -> Buffers:
         resid=torch.zeros(P, **f64), cond=torch.zeros(P, **f64), beta=torch.zeros(P, **f64),
         alpha=torch.zeros(P, **f64), alpha_real=torch.zeros(P, **f64),
         ids=torch.zeros(P, **i64), ids2=torch.zeros(P, **i64), ids3=torch.zeros(P, **i64),
-        ids4=torch.zeros(P, **i64), counts=torch.zeros(16, **i64),
+        ids4=torch.zeros(P, **i64), ids5=torch.zeros(P, **i64), counts=torch.zeros(16, **i64),
         ws=torch.zeros(max(int(ws_bytes), 256), dtype=torch.uint8, device=dev),
         ws64=torch.zeros(max(int(ws64_bytes), 256), dtype=torch.uint8, device=dev),
         wsdup=torch.zeros(max(int(L.lib().nphc_duplicates_workspace_size(P)), 256),
@@ -187,6 +188,9 @@ class Options:
 
 
 DRAIN_DEFAULT = {"fp32": 96, "fp64": 112}
+# path statuses that end tracking (everything but PENDING and HANDOFF)
+FINISHED = (L.PATH_REACHED, L.PATH_DIVERGED, L.PATH_FAIL_MINSTEP, L.PATH_FAIL_MAXSTEPS,
+            L.PATH_FAIL_NONFINITE, L.PATH_STALLED)
 
 
 def conservative_opts() -> L.TrackOpts_:
@@ -251,11 +255,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     if overlap:
         # the paths the main launch finished are refined on a second stream
         c_fin = ctypes.c_void_p(cnt.data_ptr() + 8 * 11)  # counts[11]: finished
-        L.check(lib.nphc_select(_p(b.status), P,
-                                _mask(L.PATH_REACHED, L.PATH_DIVERGED, L.PATH_FAIL_MINSTEP,
-                                      L.PATH_FAIL_MAXSTEPS, L.PATH_FAIL_NONFINITE,
-                                      L.PATH_STALLED),
-                                _p(b.ids3), c_fin, _p(b.wssel), b.wssel.numel(), s), "nphc_select")
+        L.check(lib.nphc_select(_p(b.status), P, _mask(*FINISHED), _p(b.ids3), c_fin,
+                                _p(b.wssel), b.wssel.numel(), s), "nphc_select")
         if b.side is None:
             b.side = torch.cuda.Stream(device=b.z.device)
         fork = torch.cuda.Event()
@@ -280,12 +281,27 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
             events["resume_end"].record()
     if "after_resume" in events:
         events["after_resume"]()
+    c_tail = ctypes.c_void_p(cnt.data_ptr() + 8 * 10)      # counts[10]: tail paths
+    split = overlap and opts.tail_group and prec == L.NPHC_FP32
     if handed_off and opts.tail_group:
         # the last, long paths: float64, a group of 16 lanes per path
         go = L.default_track_opts(L.NPHC_FP64).copy(resume=1, lanes_per_path=16)
-        c_tail = ctypes.c_void_p(cnt.data_ptr() + 8 * 10)  # counts[10]: tail paths
         L.check(lib.nphc_select(_p(b.status), P, _mask(L.PATH_HANDOFF), _p(b.ids4), c_tail,
                                 _p(b.wssel), b.wssel.numel(), s), "nphc_select")
+        if split:
+            # the handed-off paths the continuation finished are refined on
+            # the second stream while the lane groups track the rest
+            c_cf = ctypes.c_void_p(cnt.data_ptr() + 8 * 12)  # counts[12]
+            L.check(lib.nphc_select_list(_p(b.status), _p(b.ids), P, c_ho,
+                                         _mask(L.PATH_PENDING, *FINISHED),
+                                         _p(b.ids5), c_cf, _p(b.wssel), b.wssel.numel(), s),
+                    "nphc_select_list")
+            fork2 = torch.cuda.Event()
+            fork2.record(main)
+            b.side.wait_event(fork2)
+            refine(b.ids5, c_cf, ctypes.c_void_p(b.side.cuda_stream))
+            join = torch.cuda.Event()      # the second stream runs in order: this
+            join.record(b.side)            # also covers its first refinement
         if "tail_begin" in events:
             events["tail_begin"].record()
         L.check(lib.nphc_track_paths(B, _p(b.ids4), P, c_tail, L.NPHC_FP64, ctypes.byref(go),
@@ -294,7 +310,11 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
                                      b.ws64.numel(), s), "nphc_track_paths(tail)")
         if "tail_end" in events:
             events["tail_end"].record()
-    if overlap:
+    if split:
+        # the tail's paths; then wait for the second stream
+        refine(b.ids4, c_tail, s)
+        main.wait_event(join)
+    elif overlap:
         # the handed-off paths, once finished; then wait for the other half
         refine(b.ids, c_ho, s)
         main.wait_event(join)
