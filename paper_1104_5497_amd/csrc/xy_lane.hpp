@@ -99,6 +99,25 @@ struct UnitRhs {
     template <class T> NPHC_HD cx<T> rc(int k) const { return {M + k == j ? T(1) : T(0), T(0)}; }
 };
 
+// Pivot threshold of the elimination: 0 is partial pivoting; tau > 0 keeps
+// the diagonal pivot while it is at least tau times the largest candidate
+// (threshold pivoting, growth per step at most 1 + 1/tau).
+#ifndef NPHC_FP32_PIVOT_TAU
+#define NPHC_FP32_PIVOT_TAU 0.01f
+#endif
+template <class T> inline constexpr T kPivotTau = T(0);
+template <> inline constexpr float kPivotTau<float> = NPHC_FP32_PIVOT_TAU;
+
+// true if the predicate holds on any active lane of the wave (host: itself)
+NPHC_HD bool wave_any(bool v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_ballot_w64(v) != 0ull;
+#else
+    return v;
+#endif
+}
+
 // Solves H_z(z, t) d = -H(z, t) (newton = true) or -H_t(z, t) (the Davidenko
 // tangent, newton = false).  gamma is the homotopy constant, t in [0, 1] and
 // omt = 1 - t (passed separately so that it keeps its relative precision near
@@ -185,7 +204,8 @@ NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         NPHC_PHASE();
-        T best = abs1(R[k][k]);
+        const T diag = abs1(R[k][k]);
+        T best = diag;
         int p = k;
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
@@ -195,7 +215,16 @@ NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
             p = bigger ? i : p;
         }
         ok = ok && (best > T(0));
-        if (k + 1 < M) {
+        // threshold pivoting (kPivotTau > 0): keep the diagonal unless it is
+        // below kPivotTau times the column maximum; the exchange code runs
+        // only when some lane of the wave needs it
+        bool exchange = true;
+        if constexpr (kPivotTau<T> > T(0)) {
+            const bool need = diag < kPivotTau<T> * best;
+            p = need ? p : k;
+            exchange = wave_any(need);
+        }
+        if (k + 1 < M && exchange) {
             cx<T> rowk[M];
             const cx<T> vk = v[k];
 #pragma unroll
