@@ -116,7 +116,8 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
             while (phase != PH_DONE) {
                 const Point<double, M>& zc = (phase == PH_CERT_REAL) ? zr : z;
                 Point<double, M> d;
-                const bool sok = solve_step<double, M>(C, none, 1.0, 0.0, true, zc, d, RefineRhs<M>{j, &F});
+                const bool sok = solve_step<double, M, RefineRhs<M>, CouplingsG<double, M>, false>(
+                    C, none, 1.0, 0.0, true, zc, d, RefineRhs<M>{j, &F});
                 double dd = 0.0;
 #pragma unroll
                 for (int k = 0; k < M; ++k) dd += norm2(d.x[k]) + norm2(d.y[k]);

@@ -99,14 +99,20 @@ struct UnitRhs {
     template <class T> NPHC_HD cx<T> rc(int k) const { return {M + k == j ? T(1) : T(0), T(0)}; }
 };
 
-// Pivot threshold of the elimination: 0 is partial pivoting; tau > 0 keeps
-// the diagonal pivot while it is at least tau times the largest candidate
-// (threshold pivoting, growth per step at most 1 + 1/tau).
-#ifndef NPHC_FP32_PIVOT_TAU
-#define NPHC_FP32_PIVOT_TAU 0.01f
-#endif
-template <class T> inline constexpr T kPivotTau = T(0);
-template <> inline constexpr float kPivotTau<float> = NPHC_FP32_PIVOT_TAU;
+// Pivot threshold of the elimination in tracking solves: 0 is partial
+// pivoting; tau > 0 keeps the diagonal pivot while it is at least tau times
+// the largest candidate (threshold pivoting, growth per step at most
+// 1 + 1/tau).  Tracking solves only feed Newton corrections and predictor
+// tangents, so their rounding costs iterations, not accuracy.  Solves with
+// TRACK = false (certification) always pivot partially.  Measured on gfx950:
+// float32 gains at every M; float64 gains up to M = 11 (less spill), but
+// loses at M = 12, where it stays off.
+template <class T, int M>
+constexpr T pivot_tau()
+{
+    if constexpr (sizeof(T) == 4) return T(0.01);
+    else return M <= 11 ? T(0.01) : T(0);
+}
 
 // true if the predicate holds on any active lane of the wave (host: itself)
 NPHC_HD bool wave_any(bool v)
@@ -127,7 +133,7 @@ NPHC_HD bool wave_any(bool v)
 // Rhs::kExt: the right-hand side is supplied by rhs (rg(k): gradient row k,
 // rc(k): constraint row k), e.g. -H evaluated in a wider type; H_z is still
 // formed from z in type T.
-template <class T, int M, class Rhs = OwnRhs, class Cp = Couplings<T, M>>
+template <class T, int M, class Rhs = OwnRhs, class Cp = Couplings<T, M>, bool TRACK = true>
 NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
                         const Point<T, M>& z, Point<T, M>& d, const Rhs& rhs = Rhs{})
 {
@@ -215,12 +221,12 @@ NPHC_HD bool solve_step(const Cp& C, cx<T> gamma, T t, T omt, bool newton,
             p = bigger ? i : p;
         }
         ok = ok && (best > T(0));
-        // threshold pivoting (kPivotTau > 0): keep the diagonal unless it is
-        // below kPivotTau times the column maximum; the exchange code runs
+        // threshold pivoting (pivot_tau > 0): keep the diagonal unless it is
+        // below pivot_tau times the column maximum; the exchange code runs
         // only when some lane of the wave needs it
         bool exchange = true;
-        if constexpr (kPivotTau<T> > T(0)) {
-            const bool need = diag < kPivotTau<T> * best;
+        if constexpr (TRACK && pivot_tau<T, M>() > T(0)) {
+            const bool need = diag < pivot_tau<T, M>() * best;
             p = need ? p : k;
             exchange = wave_any(need);
         }
