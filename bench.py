@@ -57,8 +57,8 @@ FP64_VECTOR_PEAK = 78.6    # TFLOP/s, MI355X vector fp64 (AMD spec)
 # tracker sources it was measured on: reported as null once they change.
 TRACKER_SOURCES = ("track.hip", "path.hpp", "xy_lane.hpp", "cx.hpp", "common.hpp")
 MEASURED_TRAFFIC = dict(
-    sources_sha256="3015836b4b09ffb69e53db06b9c7fa7a8594a3fa5601849d4663a036521aacd8",
-    fetch_kib=83125.375, fetch_scale=1.99969, write_kib=528759.84375, write_scale=1.0)
+    sources_sha256="c5812fb48ad51f8994bceeb534e7d3dca6a20d6eae8fdf775b531a181c58415e",
+    fetch_kib=83992.75, fetch_scale=1.99968, write_kib=526967.09375, write_scale=1.0)
 
 
 def fetch_real(b):
