@@ -4,7 +4,10 @@
 //
 // Lane r < M of the group owns row r of the reduced M x M system R v = rhs
 // (see xy_lane.hpp for its derivation) and assembles it from the point z,
-// which every lane of the group holds.  Elimination uses partial pivoting
+// which every lane of the group holds.  Lane r also owns constraint row r:
+// it forms its parametrisation once, the other lanes gather the particular
+// solutions they need, and after the solve lane r forms (dx_r, dy_r), which
+// every lane then gathers.  Elimination uses partial pivoting
 // without moving rows: for column k the unused row with the largest
 // |re| + |im| is found by a 16-lane reduction, becomes pivot row k (its lane
 // is marked used) and is broadcast to the other unused rows, which eliminate
@@ -100,7 +103,18 @@ __device__ __forceinline__ void argmax_stage(T& val, int& who)
     who = take ? w2 : who;
 }
 
-// a[r] for the lane's row r (bit r of sel set)
+// maximum over the 16 lanes of the group (fmax: NaN operands are skipped)
+template <class T>
+__device__ __forceinline__ T group_max(T v)
+{
+    v = fmax(v, dpp_x<kDppXor1>(v));
+    v = fmax(v, dpp_x<kDppXor2>(v));
+    v = fmax(v, dpp_x<kDppHalfMirror>(v));
+    v = fmax(v, dpp_x<kDppMirror>(v));
+    return v;
+}
+
+// a[r] for the lane's row r (bit r of sel set; a[0] when no bit is set)
 template <class T, int M>
 __device__ __forceinline__ cx<T> pick(const cx<T> (&a)[M], unsigned sel)
 {
@@ -122,17 +136,20 @@ __device__ __forceinline__ bool group_solve_step(const GroupRow<T, M>& G, cx<T> 
     const T c2 = newton ? t : T(1);
     const bool have_row = r < M;
 
+    // --- constraint row r (lane r only; the others gather what they need)
+    const cx<T> xr = pick<T, M>(z.x, onehot), yr = pick<T, M>(z.y, onehot);
+    cx<T> ar, br, pxr, pyr;
+    constraint_row<T>(t, gt, c1, c2, xr, yr, ar, br, pxr, pyr);
+
     // --- row r of R and its right-hand side
     cx<T> R[M];
     cx<T> v = {T(0), T(0)};
     {
-        const cx<T> xr = pick<T, M>(z.x, onehot), yr = pick<T, M>(z.y, onehot);
         cx<T> sx = {G.wr, T(0)}, sy = {T(0), T(0)}, U = {T(0), T(0)}, W = {T(0), T(0)};
         const cx<T> Yr = gt * yr;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            cx<T> aj, bj, pxj, pyj;
-            constraint_row<T>(t, gt, c1, c2, z.x[j], z.y[j], aj, bj, pxj, pyj);
+            const cx<T> pxj = gshfl(pxr, j), pyj = gshfl(pyr, j);
             const T Jrj = G.Jr[j];  // zero for j = r
             sx = axpy(Jrj, z.x[j], sx);
             sy = axpy(Jrj, z.y[j], sy);
@@ -141,8 +158,6 @@ __device__ __forceinline__ bool group_solve_step(const GroupRow<T, M>& G, cx<T> 
             // off-diagonal 2 t J_rj ((g + t) y_r y_j + t x_r x_j)
             R[j] = (T(2) * t * Jrj) * (Yr * z.y[j] + t * (xr * z.x[j]));
         }
-        cx<T> ar, br, pxr, pyr;
-        constraint_row<T>(t, gt, c1, c2, xr, yr, ar, br, pxr, pyr);
         const cx<T> F = yr * sx - xr * sy;
         const cx<T> xx = xr * xr;
         const cx<T> xm1 = {xx.re - T(1), xx.im};
@@ -196,16 +211,17 @@ __device__ __forceinline__ bool group_solve_step(const GroupRow<T, M>& G, cx<T> 
         x[k] = gshfl(mine, piv[k]);
     }
 
-    // --- back to (dx, dy)
-    T mag = T(0);
+    // --- back to (dx, dy): lane r forms component r, every lane gathers all
+    const cx<T> vr = pick<T, M>(x, onehot);
+    const cx<T> dxr = fma(br, vr, pxr);
+    const cx<T> dyr = fnma(ar, vr, pyr);
+    T mag = have_row ? fmax(absmax(dxr), absmax(dyr)) : T(0);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        cx<T> ak, bk, pxk, pyk;
-        constraint_row<T>(t, gt, c1, c2, z.x[k], z.y[k], ak, bk, pxk, pyk);
-        d.x[k] = fma(bk, x[k], pxk);
-        d.y[k] = fnma(ak, x[k], pyk);
-        mag = fmax(mag, fmax(absmax(d.x[k]), absmax(d.y[k])));
+        d.x[k] = gshfl(dxr, k);
+        d.y[k] = gshfl(dyr, k);
     }
+    mag = group_max(mag);
     ok = ok && (mag - mag == T(0));
     return ok;
 }
