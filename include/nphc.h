@@ -151,7 +151,10 @@ typedef struct nphc_track_opts {
 /* Endpoint refinement and certification settings. */
 typedef struct nphc_cert_opts {
     int32_t max_iter; /* Newton iterations on F at t = 1 */
-    int32_t pad;
+    int32_t lanes_per_item; /* 1 (default; 0 means 1), 4, 8 or 16 lanes refine one endpoint:
+                               Newton runs on every lane of the group and the certificate's
+                               2m + 1 solves are split over them (lower latency for short
+                               lists, more total work); results equal to rounding */
     double tol;       /* Newton stops when ||dz|| <= tol (1 + ||z||) */
     double res_tol;   /* NONSINGULAR needs ||F||_inf < res_tol * max(1, ||z||_inf^2) ... */
     double cond_max;  /* ... and cond(F_z) < cond_max; SINGULAR: ||F|| small, cond >= cond_max */

@@ -65,10 +65,17 @@ class TrackOpts_(ctypes.Structure):
 
 
 class CertOpts_(ctypes.Structure):
-    _fields_ = [("max_iter", ctypes.c_int32), ("pad", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("res_tol", ctypes.c_double), ("cond_max", ctypes.c_double),
-                ("sing_res", ctypes.c_double), ("div_norm", ctypes.c_double),
-                ("real_tol", ctypes.c_double)]
+    _fields_ = [("max_iter", ctypes.c_int32), ("lanes_per_item", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("res_tol", ctypes.c_double),
+                ("cond_max", ctypes.c_double), ("sing_res", ctypes.c_double),
+                ("div_norm", ctypes.c_double), ("real_tol", ctypes.c_double)]
+
+    def copy(self, **kw) -> "CertOpts_":
+        o = CertOpts_()
+        ctypes.pointer(o)[0] = self
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
 
 
 class ClassOpts_(ctypes.Structure):

@@ -76,7 +76,7 @@ extern "C" void nphc_default_cert_opts(nphc_cert_opts* o)
 {
     if (!o) return;
     o->max_iter = 20;
-    o->pad = 0;
+    o->lanes_per_item = 1;
     o->tol = 1e-15;
     o->res_tol = 1e-12;
     o->cond_max = 1e10;

@@ -1,9 +1,12 @@
 // refine.hip -- float64 endpoint refinement and certification.
 //
-// Refinement runs one endpoint per lane on the structured solver of the
-// tracker (nphc::solve_step at t = 1, where H = F): Newton on F, then the
+// Refinement runs each endpoint on the structured solver of the tracker
+// (nphc::solve_step at t = 1, where H = F): Newton on F, then the
 // certificate quantities, with ||F_z^{-1}||_F from the 2m columns of the
-// inverse (one solve per unit right-hand side).
+// inverse (one solve per unit right-hand side).  One lane per endpoint, or a
+// group of G lanes per endpoint (short lists, where latency matters): the
+// group runs Newton identically on every lane and splits the certificate's
+// 2m + 1 solves over its lanes.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -58,9 +61,32 @@ struct RefineRhs {
 //              max |Im z_k| <= real_tol (certificate of a real root).
 enum { PH_NEWTON = 0, PH_CERT = 1, PH_CERT_REAL = 2, PH_DONE = 3 };
 
-template <int M>
+// sum / logical and over the G lanes of a group (G a power of two <= 64)
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ bool group_all(bool v)
+{
+    int x = v ? 1 : 0;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, G));
+    return x != 0;
+}
+
+template <int M, int G>
 __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
 {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group size");
+    // certificate rounds per phase: lane r solves columns r - 1, r - 1 + G, ...
+    // (column -1: beta); every lane of a group runs all rounds, so the group
+    // reaches the end of a phase together
+    constexpr int kRounds = (2 * M + 1 + G - 1) / G;
+    const int r = G > 1 ? int(threadIdx.x) % G : 0;
     const cx<double> none = {0.0, 0.0};
     int64_t n = A.count;
     if (A.count_dev) n = min(n, *A.count_dev);
@@ -77,8 +103,9 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
         lo = A.item_lo;
         hi = A.item_hi;
     }
-    const int64_t step = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t pos = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; pos < hi; pos += step) {
+    const int64_t step = int64_t(gridDim.x) * blockDim.x / G;
+    for (int64_t pos = lo + (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G; pos < hi;
+         pos += step) {
         const int64_t g = A.ids ? A.ids[pos] : pos;
         const int64_t sys = find_system(A.path_off, A.num_systems, g);
         CouplingsG<double, M> C;
@@ -109,15 +136,19 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
 
             Point<double, M> F;       // F at the point of the current solves
             eval_F<double, M>(C, z, F);
-            int phase = PH_NEWTON, it = 0, j = -1;
+            int phase = PH_NEWTON, it = 0, j = -1, round = 0;
             double prev = INFINITY, inv2 = 0.0, b2 = 0.0, an2 = 0.0, res = 0.0;
             bool cok = true;
             Point<double, M> zr;      // the real projection (CERT_REAL)
             while (phase != PH_DONE) {
                 const Point<double, M>& zc = (phase == PH_CERT_REAL) ? zr : z;
                 Point<double, M> d;
+                // this lane's column in a certificate round (a valid one
+                // stands in past the last column; its result is not used)
+                const bool col = (phase == PH_NEWTON) || j < 2 * M;
+                const int jj = col ? j : 0;
                 const bool sok = solve_step<double, M, RefineRhs<M>, CouplingsG<double, M>, false>(
-                    C, none, 1.0, 0.0, true, zc, d, RefineRhs<M>{j, &F});
+                    C, none, 1.0, 0.0, true, zc, d, RefineRhs<M>{jj, &F});
                 double dd = 0.0;
 #pragma unroll
                 for (int k = 0; k < M; ++k) dd += norm2(d.x[k]) + norm2(d.y[k]);
@@ -139,16 +170,26 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
                         res = norm_mod<double, M>(F);
                         an2 = jac_frob2<double, M>(C, z);
                         phase = PH_CERT;
-                        j = -1;
+                        j = r - 1;
+                        round = 0;
                         cok = true;
+                        b2 = 0.0;
                         inv2 = 0.0;
                     }
                     continue;
                 }
                 // certificate phases
-                cok = cok && sok;
-                if (j < 0) b2 = dd; else inv2 += dd;
-                if (++j < 2 * M) continue;
+                if (col) {
+                    cok = cok && sok;
+                    if (j < 0) b2 = dd; else inv2 += dd;
+                }
+                j += G;
+                if (++round < kRounds) continue;
+                if constexpr (G > 1) {
+                    b2 = group_sum<G>(b2);
+                    inv2 = group_sum<G>(inv2);
+                    cok = group_all<G>(cok);
+                }
                 if (phase == PH_CERT) {
                     resid = res;
                     if (cok) {
@@ -175,8 +216,10 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
                         }
                         eval_F<double, M>(C, zr, F);
                         phase = PH_CERT_REAL;
-                        j = -1;
+                        j = r - 1;
+                        round = 0;
                         cok = true;
+                        b2 = 0.0;
                         inv2 = 0.0;
                     } else {
                         phase = PH_DONE;
@@ -186,14 +229,17 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs A)
                     phase = PH_DONE;
                 }
             }
+            if (r == 0) {
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                A.z[(2 * k) * A.stride + g] = z.x[k].re;
-                A.z[(2 * k + 1) * A.stride + g] = z.x[k].im;
-                A.z[(2 * (M + k)) * A.stride + g] = z.y[k].re;
-                A.z[(2 * (M + k) + 1) * A.stride + g] = z.y[k].im;
+                for (int k = 0; k < M; ++k) {
+                    A.z[(2 * k) * A.stride + g] = z.x[k].re;
+                    A.z[(2 * k + 1) * A.stride + g] = z.x[k].im;
+                    A.z[(2 * (M + k)) * A.stride + g] = z.y[k].re;
+                    A.z[(2 * (M + k) + 1) * A.stride + g] = z.y[k].im;
+                }
             }
         }
+        if (r != 0) continue;   // the group's results are the same on every lane
         A.endpoint[g] = code;
         if (A.resid) A.resid[g] = resid;
         if (A.cond) A.cond[g] = cond;
@@ -223,6 +269,8 @@ extern "C" int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int6
     const int64_t total = b->path_off_host[b->num_systems];
     if (item_stride < total) return NPHC_EINVAL;
     if (!ids) count = total;
+    const int G = o->lanes_per_item <= 1 ? 1 : o->lanes_per_item;
+    if (G != 1 && G != 4 && G != 8 && G != 16) return NPHC_EINVAL;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NPHC_EHIP;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return NPHC_EHIP;
@@ -253,15 +301,21 @@ extern "C" int nphc_refine_certify(const nphc_batch* b, const int64_t* ids, int6
         A.beta = beta;
         A.alpha = alpha;
         A.alpha_real = alpha_real;
-        // one endpoint per lane, several rounds per lane
+        // G lanes per endpoint, several rounds per group
         const int64_t items = A.item_hi - A.item_lo;
         int64_t grid = int64_t(cus) * 4;
-        const int64_t need = (items + 63) / 64;
+        const int64_t need = (items * G + 63) / 64;
         if (need < grid) grid = need;
         if (grid < 1) grid = 1;
         const void* fn = nullptr;
         switch (A.M) {
-#define NPHC_RCASE(m) case m: fn = reinterpret_cast<const void*>(&refine_kernel<m>); break;
+#define NPHC_RCASE(m)                                                                      \
+    case m:                                                                                \
+        fn = G == 1 ? reinterpret_cast<const void*>(&refine_kernel<m, 1>)                  \
+           : G == 4 ? reinterpret_cast<const void*>(&refine_kernel<m, 4>)                  \
+           : G == 8 ? reinterpret_cast<const void*>(&refine_kernel<m, 8>)                  \
+                    : reinterpret_cast<const void*>(&refine_kernel<m, 16>);                \
+        break;
             NPHC_RCASE(1) NPHC_RCASE(2) NPHC_RCASE(3) NPHC_RCASE(4) NPHC_RCASE(5) NPHC_RCASE(6)
             NPHC_RCASE(7) NPHC_RCASE(8) NPHC_RCASE(9) NPHC_RCASE(10) NPHC_RCASE(11) NPHC_RCASE(12)
 #undef NPHC_RCASE

@@ -185,6 +185,9 @@ class Options:
     # refine the paths the main launch finished on a second stream while the
     # float64 continuation and tail run (they touch disjoint items)
     overlap: bool = True
+    # lanes per endpoint for refining the lane-group tail's paths (a short
+    # list on the critical path: the certificate's solves split over them)
+    tail_refine_lanes: int = 8
 
 
 DRAIN_DEFAULT = {"fp32": 96, "fp64": 112}
@@ -243,8 +246,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     c_ho = ctypes.c_void_p(cnt.data_ptr() + 8 * 9)       # counts[9]: handed off
     overlap = handed_off and opts.overlap
 
-    def refine(ids, c_list, strm):
-        L.check(lib.nphc_refine_certify(B, _p(ids), P, c_list, ctypes.byref(co), _p(b.z), stride,
+    def refine(ids, c_list, strm, o=co):
+        L.check(lib.nphc_refine_certify(B, _p(ids), P, c_list, ctypes.byref(o), _p(b.z), stride,
                                         _p(b.t), _p(b.status), _p(b.endpoint), _p(b.resid),
                                         _p(b.cond), _p(b.beta), _p(b.alpha), _p(b.alpha_real),
                                         strm), "nphc_refine_certify")
@@ -312,7 +315,7 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
             events["tail_end"].record()
     if split:
         # the tail's paths; then wait for the second stream
-        refine(b.ids4, c_tail, s)
+        refine(b.ids4, c_tail, s, co.copy(lanes_per_item=opts.tail_refine_lanes))
         main.wait_event(join)
     elif overlap:
         # the handed-off paths, once finished; then wait for the other half

@@ -14,7 +14,7 @@ import workload
 pytestmark = pytest.mark.gpu
 
 
-def _refine(J, gamma, zs):
+def _refine(J, gamma, zs, lanes=1):
     import torch
     from paper_1104_5497_amd import _lib as L, pipeline
     batch = pipeline.Batch([J], [gamma])
@@ -32,7 +32,7 @@ def _refine(J, gamma, zs):
     out = {k: torch.zeros(P, dtype=torch.float64, device=dev)
            for k in ("resid", "cond", "beta", "alpha", "alpha_real")}
     endpoint = torch.zeros(P, dtype=torch.int32, device=dev)
-    co = L.default_cert_opts()
+    co = L.default_cert_opts().copy(lanes_per_item=lanes)
     p = lambda x: ctypes.c_void_p(x.data_ptr())
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     L.check(L.lib().nphc_refine_certify(ctypes.byref(batch.c), p(ids), K, None, ctypes.byref(co),
@@ -86,3 +86,50 @@ def test_refine_restores_perturbed_roots(case):
     assert bad.size == 0, [(float(q["alpha"][i]), float(alpha2[i]), float(q["beta"][i]), float(beta[i]),
                             float(cond2[i]), float(q["cond"][i]), float(np.max(np.abs(roots[i]))))
                            for i in bad[:5]]
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_grouped_refinement_matches_one_lane(lanes):
+    """lanes_per_item > 1 (Newton on every lane of a group, the certificate's
+    2m + 1 solves split over the group) against one lane per endpoint, on
+    perturbed oracle roots plus points that fail to converge: the refined
+    points and the endpoint classes are identical (same Newton sequence); the
+    certificate sums differ only in summation order (1e-13 relative)."""
+    J = workload.disordered_ring_J(9, 1.1, np.random.default_rng(4))
+    gamma = workload.gamma_from_seed(0)
+    ref = oracle.find_all_sps(J, gamma)
+    roots = ref.z[ref.endpoint == oracle.EP_NONSINGULAR][:300]
+    rng = np.random.default_rng(9)
+    noise = (rng.standard_normal(roots.shape) + 1j * rng.standard_normal(roots.shape)) * 1e-5
+    junk = rng.standard_normal((37, roots.shape[1])) * 3 + 0j   # ragged tail, mostly not roots
+    zs = np.concatenate([roots + noise, junk])
+    print(f"grouped refinement lanes={lanes}: {zs.shape[0]} points", flush=True)
+    z1, ep1, q1 = _refine(J, gamma, zs, 1)
+    zg, epg, qg = _refine(J, gamma, zs, lanes)
+    assert np.array_equal(ep1, epg)
+    assert np.array_equal(z1, zg, equal_nan=True)
+    assert np.array_equal(q1["resid"], qg["resid"], equal_nan=True)
+    for k in ("cond", "beta", "alpha", "alpha_real"):
+        a, b = q1[k], qg[k]
+        fin = np.isfinite(a)
+        assert np.array_equal(fin, np.isfinite(b)), k
+        assert np.allclose(a[fin], b[fin], rtol=1e-13, atol=0), k
+
+
+def test_grouped_refinement_rejects_bad_group_size():
+    import torch
+    from paper_1104_5497_amd import _lib as L, pipeline
+    batch = pipeline.Batch([workload.clean_ring_J(5, 1.0)], [workload.gamma_from_seed(0)])
+    P, n = batch.num_items, batch.n_max
+    dev = batch.device
+    z = torch.zeros((2 * n, P), dtype=torch.float64, device=dev)
+    t = torch.ones(P, dtype=torch.float64, device=dev)
+    st = torch.zeros(P, dtype=torch.int32, device=dev)
+    ep = torch.zeros(P, dtype=torch.int32, device=dev)
+    p = lambda x: ctypes.c_void_p(x.data_ptr())
+    for bad in (2, 3, 32):
+        co = L.default_cert_opts().copy(lanes_per_item=bad)
+        rc = L.lib().nphc_refine_certify(ctypes.byref(batch.c), None, P, None, ctypes.byref(co),
+                                         p(z), P, p(t), p(st), p(ep), None, None, None, None, None,
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == L.NPHC_EINVAL
