@@ -165,11 +165,16 @@ class Options:
     precision: str = "fp32"
     track: Optional[L.TrackOpts_] = None        # defaults per precision
     resume: Optional[L.TrackOpts_] = None       # float64 continuation of handed-off paths
-    retrack: Optional[L.TrackOpts_] = None      # float64 re-tracking (hmax divided by 4 per round)
+    retrack: Optional[L.TrackOpts_] = None      # float64 re-tracking (see retrack_shrink)
     cert: Optional[L.CertOpts_] = None
     classify: Optional[L.ClassOpts_] = None
     dup_tol: float = 1e-8
     retrack_rounds: int = 2
+    # hmax is divided by this in every re-track round.  A quarter per round
+    # spent 37 ms at N = 11 on its second round (hmax / 16) for paths that
+    # stayed failed; halving recovers as many (N = 11 and 13) at a third of
+    # the cost.
+    retrack_shrink: float = 2.0
     # Tails: once a launch's queue is empty, its paths in flight get at most
     # this many more steps, then the lane-group tracker (16 lanes per path,
     # float64) finishes them.  None: the default for the precision; 0: off.
@@ -264,10 +269,17 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
             b.side = torch.cuda.Stream(device=b.z.device)
         fork = torch.cuda.Event()
         fork.record(main)
+
+    def side_refine_finished():
+        # enqueued after the continuation's launch, so that the continuation
+        # reaches the hardware first (the refinement then fills its gaps);
+        # it depends only on the fork recorded before the continuation
         b.side.wait_event(fork)
         refine(b.ids3, c_fin, ctypes.c_void_p(b.side.cuda_stream))
-        join = torch.cuda.Event()
-        join.record(b.side)
+        ev = torch.cuda.Event()
+        ev.record(b.side)
+        return ev
+
     if handed_off and prec == L.NPHC_FP32:
         # float64 continuation of the paths the float32 tracker handed off,
         # one path per lane (its own tail left to the lane groups below)
@@ -282,6 +294,8 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
                                      b.ws64.numel(), s), "nphc_track_paths(resume)")
         if "resume_end" in events:
             events["resume_end"].record()
+    if overlap:
+        join = side_refine_finished()
     if "after_resume" in events:
         events["after_resume"]()
     c_tail = ctypes.c_void_p(cnt.data_ptr() + 8 * 10)      # counts[10]: tail paths
@@ -338,7 +352,7 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
     dedupe()
     hmax = rt.hmax
     for r in range(opts.retrack_rounds):
-        hmax /= 4.0
+        hmax /= opts.retrack_shrink
         o = rt.copy(h0=min(rt.h0, hmax), hmax=hmax)
         c_rt = ctypes.c_void_p(cnt.data_ptr() + 8 * (2 + r))  # counts[2+r]: re-tracked
         L.check(lib.nphc_select(_p(b.endpoint), P, _mask(L.END_FAIL, L.END_DUPLICATE), _p(b.ids),
