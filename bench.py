@@ -58,7 +58,7 @@ FP64_VECTOR_PEAK = 78.6    # TFLOP/s, MI355X vector fp64 (AMD spec)
 TRACKER_SOURCES = ("track.hip", "path.hpp", "xy_lane.hpp", "cx.hpp", "common.hpp")
 MEASURED_TRAFFIC = dict(
     sources_sha256="c5812fb48ad51f8994bceeb534e7d3dca6a20d6eae8fdf775b531a181c58415e",
-    fetch_kib=84176.3125, fetch_scale=1.99968, write_kib=521218.5625, write_scale=1.0)
+    fetch_kib=84158.1875, fetch_scale=1.99967, write_kib=522320.4375, write_scale=1.0)
 
 
 def fetch_real(b):
