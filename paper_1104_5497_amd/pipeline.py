@@ -212,10 +212,11 @@ def conservative_opts() -> L.TrackOpts_:
 def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None, stream=None,
         events: Optional[Dict] = None) -> Buffers:
     """Enqueue the whole pipeline on the stream (no host synchronisation).
-    events: optional dict of torch.cuda.Event recorded (same stream) around the
-    main tracking launch ("track_begin"/"track_end") and the float64
-    continuation ("resume_begin"/"resume_end"), and an optional callable
-    "after_track" invoked right after the main tracking launch is enqueued."""
+    events: optional dict of torch.cuda.Event, recorded on the pipeline's
+    stream around the main tracking launch ("track_begin"/"track_end"), the
+    float64 continuation ("resume_begin"/"resume_end") and the lane-group
+    tail ("tail_begin"/"tail_end"), and optional callables "after_track" and
+    "after_resume", invoked right after those launches are enqueued."""
     lib = L.lib()
     prec = PREC[opts.precision]
     b = bufs or allocate(batch, opts.precision)
@@ -237,13 +238,13 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
 
     events = events or {}
     if "track_begin" in events:
-        events["track_begin"].record()
+        events["track_begin"].record(main)
     L.check(lib.nphc_track_paths(B, None, P, None, prec, ctypes.byref(to), _p(b.z), stride,
                                  _p(b.t), _p(b.status), _p(b.accepted), _p(b.rejected),
                                  _p(b.solves), _p(b.h), _p(b.ws), b.ws.numel(), s),
             "nphc_track_paths")
     if "track_end" in events:
-        events["track_end"].record()
+        events["track_end"].record(main)
     if "after_track" in events:
         events["after_track"]()
     handed_off = (to.handoff_rejects > 0 or to.handoff_norm > 0 or to.handoff_steps > 0 or
@@ -287,13 +288,13 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
             resume=1,
             drain_steps=opts.cont_drain if opts.tail_group and not opts.deterministic else 0)
         if "resume_begin" in events:
-            events["resume_begin"].record()
+            events["resume_begin"].record(main)
         L.check(lib.nphc_track_paths(B, _p(b.ids), P, c_ho, L.NPHC_FP64, ctypes.byref(ro),
                                      _p(b.z), stride, _p(b.t), _p(b.status), _p(b.accepted),
                                      _p(b.rejected), _p(b.solves), _p(b.h), _p(b.ws64),
                                      b.ws64.numel(), s), "nphc_track_paths(resume)")
         if "resume_end" in events:
-            events["resume_end"].record()
+            events["resume_end"].record(main)
     if overlap:
         join = side_refine_finished()
     if "after_resume" in events:
@@ -320,13 +321,13 @@ def run(batch: Batch, opts: Options = Options(), bufs: Optional[Buffers] = None,
             join = torch.cuda.Event()      # the second stream runs in order: this
             join.record(b.side)            # also covers its first refinement
         if "tail_begin" in events:
-            events["tail_begin"].record()
+            events["tail_begin"].record(main)
         L.check(lib.nphc_track_paths(B, _p(b.ids4), P, c_tail, L.NPHC_FP64, ctypes.byref(go),
                                      _p(b.z), stride, _p(b.t), _p(b.status), _p(b.accepted),
                                      _p(b.rejected), _p(b.solves), _p(b.h), _p(b.ws64),
                                      b.ws64.numel(), s), "nphc_track_paths(tail)")
         if "tail_end" in events:
-            events["tail_end"].record()
+            events["tail_end"].record(main)
     if split:
         # the tail's paths; then wait for the second stream
         refine(b.ids4, c_tail, s, co.copy(lanes_per_item=opts.tail_refine_lanes))
